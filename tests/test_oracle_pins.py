@@ -1,0 +1,340 @@
+"""Pins of the FP64 oracle to facts the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: textbook
+counts, library routines (scipy's chessboard distance transform, numpy's
+binary16 rounding), the closed-form limit direction of Theorem 4.1
+(eqn:limitDirection / eqn:ctgf_limits), exactness on linear data transported
+along the guide (Sec. 3.3, 4.2), the maximum principle implied by non-negative
+weights (Algorithm 1), the iteration bound of Theorem 5.2, lattice symmetries.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synthetic as syn
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------
+# the neighbourhood
+
+
+def test_ball_sizes_are_gauss_circle_counts():
+    # Gauss circle problem: lattice points with n^2 + m^2 <= r^2 number
+    # 1, 5, 13, 29, 49, 81 for r = 0..5; the ball excludes the centre.
+    for r, n in ((1, 5), (2, 13), (3, 29), (4, 49), (5, 81)):
+        offs = oracle.offsets(float(r))
+        assert len(offs) == n - 1
+        assert (0, 0) not in offs
+        assert len(set(offs)) == len(offs)
+        assert all(a * a + b * b <= r * r for a, b in offs)
+
+
+def test_ball_order_m_then_n():
+    offs = oracle.offsets(3.0)
+    assert offs == sorted(offs, key=lambda t: (t[1], t[0]))
+
+
+def test_f16_rounding_matches_numpy():
+    rng = np.random.default_rng(7)
+    vals = np.concatenate([
+        rng.uniform(-2, 2, 20000),
+        rng.uniform(0, 1e-4, 5000),          # subnormal range of binary16
+        rng.uniform(60000, 70000, 2000),     # overflow boundary
+        (np.arange(-3000, 3000) + 0.5) * 2.0 ** -11,  # exact ties
+        np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 2 ** -24, 2 ** -25, 3 * 2 ** -26]),
+    ])
+    with np.errstate(over="ignore"):
+        ref = vals.astype(np.float16).astype(np.float64)
+    got = np.array([oracle.round_f16(v) for v in vals])
+    np.testing.assert_array_equal(got, ref)
+
+
+# ----------------------------------------------------------------------------
+# constants, maximum principle, shells
+
+
+def _random_problem(seed, H=40, W=48, C=3):
+    rng = np.random.default_rng(seed)
+    img, lab, g = syn.random_tiny(rng, H, W, C=C, p_hole=0.3, p_bystander=0.08)
+    return img, lab, g
+
+
+@pytest.mark.parametrize("ghost", [True, False])
+@pytest.mark.parametrize("c", [-1.0, 0.05])
+def test_constant_image_is_reproduced(ghost, c):
+    img, lab, g = _random_problem(11)
+    const = np.array([0.25, 0.7, 1.0 / 3.0], dtype=np.float32).astype(np.float64)
+    img[:] = const
+    r = oracle.fill(img, lab, g, eps=3.0, mu=50.0, c=c, ghost=ghost)
+    filled = r.shell >= 0
+    assert filled.sum() > 100
+    # weights are normalised (Algorithm 1): a constant is reproduced up to
+    # the rounding of one weighted quotient
+    err = np.abs(r.u[filled] - const[None, :])
+    assert err.max() <= 8 * np.finfo(np.float64).eps
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("ghost", [True, False])
+def test_maximum_principle(seed, ghost):
+    img, lab, g = _random_problem(seed)
+    r = oracle.fill(img, lab, g, eps=3.0, mu=float(10 * seed), ghost=ghost)
+    readable = lab == 0
+    filled = r.shell >= 0
+    assert filled.any()
+    lo = img[readable].min(axis=0).astype(np.float64)
+    hi = img[readable].max(axis=0).astype(np.float64)
+    tol = 4 * np.finfo(np.float64).eps
+    assert (r.u[filled] >= lo - tol).all() and (r.u[filled] <= hi + tol).all()
+
+
+def _interior_holes(seed, H=64, W=64):
+    rng = np.random.default_rng(seed)
+    noise = ndimage.gaussian_filter(rng.normal(size=(H, W)), 3.0)
+    hole = noise > np.quantile(noise, 0.6)
+    hole[:4, :] = hole[-4:, :] = False
+    hole[:, :4] = hole[:, -4:] = False
+    lab = hole.astype(np.uint8)
+    img = rng.uniform(0, 1, size=(H, W, 2)).astype(np.float32)
+    ang = rng.uniform(0, 2 * math.pi, size=(H, W))
+    g = np.stack([np.cos(ang), np.sin(ang)], -1).astype(np.float32)
+    return img, lab, g
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lattice_onion_shells_are_chessboard_layers(seed):
+    # With the lattice ball (eps >= sqrt 2) every active pixel has a readable
+    # 8-neighbour inside its ball, so onion order fills the 8-connected
+    # distance layers: shell = chessboard distance to the readable set - 1.
+    img, lab, g = _interior_holes(seed)
+    r = oracle.fill(img, lab, g, eps=3.0, mu=50.0, ghost=False)
+    d = ndimage.distance_transform_cdt(lab == 1, metric="chessboard")
+    expect = np.where(lab == 1, d - 1, -1)
+    np.testing.assert_array_equal(r.shell, expect)
+    # Theorem 5.2: K <= ceil(sqrt(N) / 2) when D touches neither B nor the border
+    N = int((lab == 1).sum())
+    assert r.K <= math.ceil(math.sqrt(N) / 2)
+    assert r.n_filled == N and r.n_unfilled == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_ghost_shells_never_precede_lattice_shells(seed):
+    # The ghost ball can only make a pixel wait (no usable ghost point), never
+    # fill it earlier than the lattice ball's onion order.
+    img, lab, g = _interior_holes(seed)
+    rl = oracle.fill(img, lab, g, eps=3.0, mu=50.0, ghost=False)
+    rg = oracle.fill(img, lab, g, eps=3.0, mu=50.0, ghost=True)
+    filled = rg.shell >= 0
+    assert (rg.shell[filled] >= rl.shell[filled]).all()
+
+
+def test_shells_partition_the_hole_and_stats():
+    img, lab, g = _random_problem(5)
+    r = oracle.fill(img, lab, g, eps=3.0, mu=50.0)
+    hole = lab == 1
+    s = r.shell
+    assert ((s >= 0) | (s == -3))[hole].all()
+    assert (s[lab == 0] == -1).all() and (s[lab == 2] == -2).all()
+    assert r.n_filled + r.n_unfilled == hole.sum()
+    assert r.K == (s.max() + 1 if (s >= 0).any() else 0)
+    # every shell index below K is used (each shell fills at least one pixel)
+    assert set(np.unique(s[s >= 0]).tolist()) == set(range(r.K))
+    assert r.fill_hist[0, :r.K].sum() == r.n_filled
+
+
+def test_stall_inside_bystanders_is_reported():
+    H, W = 20, 20
+    lab = np.zeros((H, W), np.uint8)
+    lab[5:15, 5:15] = 2
+    lab[8:12, 8:12] = 1          # enclosed by bystanders: never active
+    lab[0:2, 0:3] = 1            # ordinary hole at the image corner
+    img = np.full((H, W, 1), 0.5, np.float32)
+    img[8:12, 8:12] = 0.125
+    g = np.zeros((H, W, 2), np.float32)
+    g[..., 0] = 1.0
+    r = oracle.fill(img, lab, g, eps=3.0, mu=50.0)
+    assert (r.shell[8:12, 8:12] == -3).all()
+    assert (r.u[8:12, 8:12] == 0.125).all()   # input colour kept
+    assert (r.shell[0:2, 0:3] >= 0).all()
+    assert r.n_unfilled == 16
+
+
+def test_max_shells_resume_is_equivalent():
+    img, lab, g = _random_problem(9, H=48, W=56)
+    full = oracle.fill(img, lab, g, eps=3.0, mu=50.0)
+    assert full.K >= 4
+    m = 2
+    part = oracle.fill(img, lab, g, eps=3.0, mu=50.0, max_shells=m)
+    assert part.K == m
+    lab2 = lab.copy()
+    lab2[part.shell >= 0] = 0
+    rest = oracle.fill(part.u, lab2, g, eps=3.0, mu=50.0)
+    s = np.where(rest.shell >= 0, rest.shell + m, part.shell)
+    s = np.where((lab == 1) & (part.shell >= 0), part.shell, s)
+    np.testing.assert_array_equal(s, full.shell)
+    np.testing.assert_array_equal(rest.u, full.u)
+
+
+# ----------------------------------------------------------------------------
+# symmetries of the lattice
+
+
+def _sym_problem():
+    rng = np.random.default_rng(21)
+    img, lab, g = syn.random_tiny(rng, 30, 38, C=2, p_hole=0.35, p_bystander=0.1)
+    # exact angles that put ghost points on lattice lines
+    g[::3, ::2] = np.array([math.cos(math.radians(30)), math.sin(math.radians(30))], np.float32)
+    g[1::4, ::3] = np.array([0.0, 1.0], np.float32)
+    g = np.where((lab == 1)[..., None], g, np.float32(0))
+    return img, lab, g
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.05])
+def test_guide_sign_flip_is_a_symmetry(c):
+    img, lab, g = _sym_problem()
+    a = oracle.fill(img, lab, g, c=c)
+    b = oracle.fill(img, lab, -g, c=c)
+    np.testing.assert_array_equal(a.shell, b.shell)
+    np.testing.assert_allclose(a.u, b.u, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["transpose", "flip_x", "flip_y"])
+def test_lattice_symmetries(kind):
+    img, lab, g = _sym_problem()
+    a = oracle.fill(img, lab, g)
+    if kind == "transpose":
+        img2, lab2 = img.transpose(1, 0, 2), lab.T
+        g2 = g.transpose(1, 0, 2)[..., ::-1]
+        back = lambda s: s.T if s.ndim == 2 else s.transpose(1, 0, 2)
+    elif kind == "flip_x":
+        img2, lab2 = img[:, ::-1], lab[:, ::-1]
+        g2 = g[:, ::-1] * np.array([-1, 1], np.float32)
+        back = lambda s: s[:, ::-1]
+    else:
+        img2, lab2 = img[::-1], lab[::-1]
+        g2 = g[::-1] * np.array([1, -1], np.float32)
+        back = lambda s: s[::-1]
+    b = oracle.fill(np.ascontiguousarray(img2), np.ascontiguousarray(lab2),
+                    np.ascontiguousarray(g2))
+    np.testing.assert_array_equal(back(b.shell), a.shell)
+    np.testing.assert_allclose(back(b.u), a.u, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# transport along the guide: Theorem 4.1 and the kink fix
+
+
+def _limit_direction(theta, r, mu, ghost):
+    """eqn:limitDirection evaluated directly: weighted centre of mass of the
+    part of the (rotated) ball that lies at least one row inside the known
+    half plane (known rows have smaller y in array coordinates)."""
+    gx, gy = math.cos(theta), math.sin(theta)
+    a = mu * mu / (2.0 * r * r)
+    num = np.zeros(2)
+    den = 0.0
+    for m in range(-r, r + 1):
+        for n in range(-r, r + 1):
+            if (n, m) == (0, 0) or n * n + m * m > r * r:
+                continue
+            # b~_r^-: points n*ghat + m*ghat_perp (the same set as R(B_r))
+            if ghost:
+                y = n * np.array([gx, gy]) + m * np.array([-gy, gx])
+            else:
+                y = np.array([float(n), float(m)])
+            if y[1] > -1:
+                continue
+            t = -gy * y[0] + gx * y[1]
+            w = math.exp(-a * t * t) / math.hypot(*y)
+            num += w * y
+            den += w
+    return num / den
+
+
+def _half_plane(theta, r, mu, ghost, f, Hk=6, Hh=80):
+    W = 2 * r * Hh + 64
+    H = Hk + Hh
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    img = f(xx, yy)[..., None]
+    lab = np.zeros((H, W), np.uint8)
+    lab[Hk:, :] = 1
+    g = np.zeros((H, W, 2), np.float32)
+    g[..., 0] = np.float32(math.cos(theta))
+    g[..., 1] = np.float32(math.sin(theta))
+    res = oracle.fill(img, lab, g, eps=float(r), mu=mu, ghost=ghost)
+    return res, img[..., 0], W
+
+
+CASES = ([(3, 50.0, gh) for gh in (False, True)] + [(5, 10.0, gh) for gh in (False, True)]
+         + [(5, 100.0, True)])
+
+
+@pytest.mark.parametrize("r,mu,ghost", CASES)
+def test_transport_direction_matches_limit_formula(r, mu, ghost):
+    # f = x; far from the side borders u(x, y) = x + e(y) and e grows by
+    # -g*_x / g*_y per row (transport along g*); 60 rows average out the
+    # period of the row recurrence.
+    worst = 0.0
+    for deg in range(5, 180, 20):
+        th = math.radians(deg)
+        gs = _limit_direction(th, r, mu, ghost)
+        res, _, W = _half_plane(th, r, mu, ghost, lambda x, y: x)
+        u = res.u[:, W // 2, 0]
+        slope = (u[-1] - u[-61]) / 60.0
+        pred = math.degrees(math.atan2(1.0, gs[0] / gs[1]))
+        meas = math.degrees(math.atan2(1.0, -slope))
+        worst = max(worst, abs(pred - meas))
+    assert worst < 1e-4
+
+
+@pytest.mark.parametrize("deg", [30, 45, 60, 73, 90, 120, 150])
+@pytest.mark.parametrize("r,mu", [(3, 50.0), (5, 100.0)])
+def test_ghost_ball_transports_ramps_without_kink(deg, r, mu):
+    # Data linear with gradient orthogonal to g is reproduced exactly when the
+    # limit direction is parallel to g (Theorem 4.1 with the rotated ball,
+    # angles above the critical arcsin(1/r)): bilinear interpolation is exact
+    # on linear data, so every fill equals f up to rounding.
+    th = math.radians(deg)
+    gx, gy = float(np.float32(math.cos(th))), float(np.float32(math.sin(th)))
+    f = lambda x, y: 0.3 + 0.01 * (-gy * x + gx * y)
+    res, fx, W = _half_plane(th, r, mu, True, f, Hh=24)
+    cone = r * 25
+    sl = slice(cone, W - cone)
+    err = np.abs(res.u[6:, sl, 0] - fx[6:, sl])
+    assert err.max() < 1e-12
+
+
+def test_ghost_ball_kinks_below_critical_angle_and_lattice_kinks_at_73():
+    # Below arcsin(1/r) the rotated ball has no usable point on the guide line
+    # in the first shell and the ramp bends (Sec. 4.2); the lattice ball bends
+    # at 73 degrees (Sec. 3.3).
+    for deg, ghost in ((10.0, True), (73.0, False)):
+        th = math.radians(deg)
+        gx, gy = float(np.float32(math.cos(th))), float(np.float32(math.sin(th)))
+        f = lambda x, y: 0.3 + 0.01 * (-gy * x + gx * y)
+        res, fx, W = _half_plane(th, 3, 50.0, ghost, f, Hh=24)
+        sl = slice(80, W - 80)
+        assert np.abs(res.u[6:, sl, 0] - fx[6:, sl]).max() > 1e-3
+
+
+def test_paper_connect_lines_claims():
+    """Fixture from Sec. 3.3 (Fig. connectLine): with eps = 3 px and mu = 50,
+    coherence transport given g at 73 degrees extrapolates along (0, 1); both
+    methods succeed for a vertical line; Guidefill succeeds at 73 degrees."""
+    with open(os.path.join(GOLDEN, "connect_lines.json")) as fh:
+        fix = json.load(fh)
+    for case in fix["cases"]:
+        th = math.radians(case["theta_deg"])
+        ghost = case["method"] == "guidefill"
+        res, _, W = _half_plane(th, fix["eps"], fix["mu"], ghost, lambda x, y: x)
+        u = res.u[:, W // 2, 0]
+        slope = (u[-1] - u[-61]) / 60.0
+        meas = math.degrees(math.atan2(1.0, -slope))
+        assert abs(meas - case["transport_deg"]) <= case["tol_deg"], (case, meas)
