@@ -1,0 +1,155 @@
+/*
+ * guidefill.h -- C ABI of the MI355X (gfx950) shell-fill library.
+ *
+ * The library fills the inpainting domain D_h of an image shell by shell
+ * (Hocking, MacKenzie, Schoenlieb, "Guidefill", arXiv 1611.05319, Sec. 3,
+ * Algorithm 1): at shell k every pixel of the active boundary of D^(k) that is
+ * ready receives the normalised weighted average of the readable points of its
+ * neighbourhood, with the weights of eqn:weight
+ *     w(x, y) = exp(-mu^2 / (2 eps^2) (g_perp(x) . (y - x))^2) / |y - x|,
+ * over the rotated ball of ghost pixels (Sec. 3.1, 3.3; bilinear extension
+ * eqn:bilinearDef) or the lattice ball; ready is "has a readable point" (onion
+ * order) or confidence > c (eqn:confidence, eqn:ready, Sec. 3.4).  Only the
+ * pixels of the tracked active front get lanes (Sec. 3.5, "with tracking"), or
+ * every pixel gets a lane in every shell ("without tracking").
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers owned by the caller; the library
+ *     allocates no memory.  `stream` is a hipStream_t (NULL: default stream).
+ *     Calls are asynchronous on `stream`; argument errors are reported
+ *     synchronously, device-side findings (label errors, unfilled pixels) in
+ *     the stats array after the stream is synchronised.
+ *   - Images are B x H x W x C, interleaved channels (HWC per frame), frames
+ *     contiguous; element type GF_F32 (binary32) or GF_F16 (binary16 storage;
+ *     arithmetic is FP64 in either case).  1 <= C <= 4.
+ *   - label: B x H x W uint8, 0 = readable, 1 = inpaint (D_h), 2 = bystander
+ *     (B_h, neither filled nor read, Sec. 2.1).  Other values are reported
+ *     as label errors and treated as bystanders.
+ *   - guide: B x H x W x 2 binary32 (gx, gy), x along columns, y along rows;
+ *     read on label-1 pixels only; not normalised (|g| scales the weights).
+ *   - shell: B x H x W int32 map: -1 readable, -2 bystander, k >= 0 filled in
+ *     shell k, -3 never filled (input colour kept).
+ *   - Frames are independent; one call fills all of them.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef GUIDEFILL_H
+#define GUIDEFILL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GF_OK = 0,
+    GF_EINVAL = -1,     /* bad argument (null pointer, size, parameter, workspace too small) */
+    GF_EDEVICE = -2,    /* a HIP call failed (launch, occupancy query, ...) */
+    GF_EUNSUPPORTED = -3 /* valid request outside what this build supports */
+} gf_status;
+
+typedef enum { GF_F32 = 0, GF_F16 = 1 } gf_dtype;
+
+typedef struct {
+    double eps;         /* radius of the ball in pixels, 1 <= eps <= 9 (Sec. 3.1) */
+    double mu;          /* anisotropy of the weights, mu > 0 (eqn:weight) */
+    double c;           /* < 0: onion order; >= 0: smart order threshold (eqn:ready) */
+    int32_t ghost;      /* 1: rotated ball with ghost pixels; 0: lattice ball */
+    int32_t tracking;   /* 1: lanes for the tracked front only; 0: one lane per pixel per shell */
+    int32_t max_shells; /* 0: run until no pixel is ready; n > 0: stop after n shells */
+    int32_t group;      /* lanes cooperating on one pixel: 0 (auto), 32 or 64 */
+    int32_t blocks_per_cu; /* persistent workgroups per compute unit: 0 (auto) or 1..8 */
+    int32_t reserved;
+} gf_params;
+
+/* Layout of the int32 stats array written by gf_fill / gf_fill_batched
+ * (device memory, 8 + 4 * B entries): */
+enum {
+    GF_STAT_SHELLS = 0,      /* number of shells that filled at least one pixel (K) */
+    GF_STAT_FILLED = 1,      /* pixels filled, all frames */
+    GF_STAT_HOLE = 2,        /* label-1 pixels, all frames */
+    GF_STAT_MAX_FRONT = 3,   /* largest active front (lanes requested in one shell) */
+    GF_STAT_LABEL_ERR = 4,   /* label values outside {0, 1, 2} */
+    GF_STAT_ORDER_TRUNC = 5, /* 1 if shell_offsets was too short for K + 1 entries */
+    GF_STAT_FRAME0 = 8,      /* then per frame f at 8 + 4 f: K_f, filled_f, hole_f, 0 */
+    GF_STAT_PER_FRAME = 4
+};
+
+/*
+ * Bytes of workspace gf_fill_batched needs for B frames of H x W (front lists,
+ * control words).  The workspace is device memory, any content, 256-byte
+ * aligned.
+ */
+size_t gf_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
+
+/*
+ * Fill B frames (Algorithm 1, all shells, one persistent launch).
+ *   img_in      B*H*W*C of dt, read only.
+ *   img_out     B*H*W*C of dt.  May equal img_in (in place: only filled
+ *               pixels are written); otherwise every pixel is written (the
+ *               input colour where nothing is filled).
+ *   label, guide, shell_out: as above; shell_out is required.
+ *   stats       int32[8 + 4*B], required.
+ *   order_out   nullable; int32[B*H*W]: frame*H*W + pixel of every filled
+ *               pixel, grouped by shell (the input of gf_fill_backward).
+ *   shell_offsets nullable (required with order_out); int32[kcap]: entry k is
+ *               the start of shell k in order_out, entry K its end.  If
+ *               K + 1 > kcap the fill still completes and
+ *               stats[GF_STAT_ORDER_TRUNC] is set.
+ *   front_hist  nullable; int32[kcap]: active front size of each shell.
+ *   workspace   >= gf_workspace_size(...) bytes.
+ * Returns GF_OK or GF_EINVAL / GF_EUNSUPPORTED / GF_EDEVICE.
+ */
+gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W, int C,
+                          gf_dtype dt, const uint8_t *label, const float *guide,
+                          const gf_params *p, int32_t *shell_out, int32_t *stats,
+                          int32_t *order_out, int32_t *shell_offsets, int32_t *front_hist,
+                          int kcap, void *workspace, size_t ws_bytes, void *stream);
+
+/* One frame: gf_fill_batched with B = 1. */
+gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,
+                  const uint8_t *label, const float *guide, const gf_params *p,
+                  int32_t *shell_out, int32_t *stats, void *workspace, size_t ws_bytes,
+                  void *stream);
+
+/*
+ * Reverse-mode derivative of a completed fill (this build's extension; the
+ * fill is linear in the known colours, Algorithm 1).  Replays the shells from
+ * last to first over the forward's order_out / shell_offsets, recomputing the
+ * ghost geometry and weights from the shell map instead of storing them.
+ *   grad_out    B*H*W*C binary32: dL/d img_out.
+ *   img_out     the forward's output (dt), shell: its shell map.
+ *   order, shell_offsets, K: the forward's order_out, shell_offsets and
+ *               stats[GF_STAT_SHELLS].
+ *   grad_img    B*H*W*C binary32: dL/d img_in (readable and bystander pixels
+ *               and never-filled hole pixels pass grad_out through; filled
+ *               hole pixels get 0).  May equal grad_out.
+ *   grad_guide  B*H*W*2 binary32: dL/d guide on filled pixels, 0 elsewhere.
+ *   p           the forward's parameters (eps, mu, ghost are used).
+ * Returns GF_OK or GF_EINVAL / GF_EUNSUPPORTED / GF_EDEVICE.
+ */
+gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, int H, int W, int C,
+                           gf_dtype dt, const uint8_t *label, const float *guide,
+                           const int32_t *shell, const int32_t *order,
+                           const int32_t *shell_offsets, int K, const gf_params *p,
+                           float *grad_img, float *grad_guide, void *workspace,
+                           size_t ws_bytes, void *stream);
+
+/* Bytes of workspace gf_fill_backward needs. */
+size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
+
+/* Text for a status code (static storage). */
+const char *gf_status_string(gf_status s);
+
+/* Last HIP error text recorded by this thread (static thread-local storage). */
+const char *gf_last_error(void);
+
+/* ABI version: 1. */
+int gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GUIDEFILL_H */

@@ -1,0 +1,307 @@
+"""MI355X shell fill of Guidefill (arXiv 1611.05319): Python binding.
+
+Argument marshalling only: every step of the fill runs in the HIP library
+`libguidefill.so` (built from `csrc/guidefill.hip`, C ABI in
+`include/guidefill.h`).  PyTorch supplies device memory and the stream.  There
+is no CPU fallback: without the built library or a HIP device every call
+raises.
+
+    fill(img, label, guide, eps=3, mu=50)          one frame  (H x W x C)
+    fill_batched(img, label, guide, ...)           B frames   (B x H x W x C)
+    fill_backward(...)                             reverse-mode derivative
+    GuidefillFn.apply(img, theta, label, ...)      autograd w.r.t. the image and
+                                                   the guide angle, g = (cos, sin)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "Params", "FillResult", "fill", "fill_batched", "fill_backward", "GuidefillFn",
+    "library_path", "load", "stats_fields",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libguidefill.so")
+_lib = None
+_lock = threading.Lock()
+
+GF_F32, GF_F16 = 0, 1
+_STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "unsupported request"}
+STAT_SHELLS, STAT_FILLED, STAT_HOLE, STAT_MAX_FRONT, STAT_LABEL_ERR, STAT_ORDER_TRUNC = range(6)
+STAT_FRAME0, STAT_PER_FRAME = 8, 4
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("mu", ctypes.c_double), ("c", ctypes.c_double),
+                ("ghost", ctypes.c_int32), ("tracking", ctypes.c_int32),
+                ("max_shells", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """Fill parameters (gf_params).  c < 0: onion order; c >= 0: smart order."""
+
+    eps: float = 3.0
+    mu: float = 50.0
+    c: float = -1.0
+    ghost: bool = True
+    tracking: bool = True
+    max_shells: int = 0
+    group: int = 0
+    blocks_per_cu: int = 0
+
+    def c_struct(self) -> _Params:
+        return _Params(float(self.eps), float(self.mu), float(self.c), int(bool(self.ghost)),
+                       int(bool(self.tracking)), int(self.max_shells), int(self.group),
+                       int(self.blocks_per_cu), 0)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: build it with `python -m paper_1611_05319_amd.build`")
+        lib = ctypes.CDLL(_LIB_PATH)
+        P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        PP = ctypes.POINTER(_Params)
+        lib.gf_workspace_size.argtypes = [I, I, I, I, I, PP]
+        lib.gf_workspace_size.restype = Z
+        lib.gf_backward_workspace_size.argtypes = [I, I, I, I, I, PP]
+        lib.gf_backward_workspace_size.restype = Z
+        lib.gf_fill_batched.argtypes = [P, P, I, I, I, I, I, P, P, PP, P, P, P, P, P, I, P, Z, P]
+        lib.gf_fill_batched.restype = I
+        lib.gf_fill.argtypes = [P, P, I, I, I, I, P, P, PP, P, P, P, Z, P]
+        lib.gf_fill.restype = I
+        lib.gf_fill_backward.argtypes = [P, P, I, I, I, I, I, P, P, P, P, P, I, PP, P, P, P, Z, P]
+        lib.gf_fill_backward.restype = I
+        lib.gf_status_string.argtypes = [I]
+        lib.gf_status_string.restype = ctypes.c_char_p
+        lib.gf_last_error.argtypes = []
+        lib.gf_last_error.restype = ctypes.c_char_p
+        lib.gf_version.argtypes = []
+        lib.gf_version.restype = I
+        _lib = lib
+        return lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        lib = load()
+        msg = lib.gf_status_string(rc).decode()
+        detail = lib.gf_last_error().decode()
+        raise RuntimeError(f"{what} failed: {msg} ({rc}) {detail}")
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return GF_F32
+    if t.dtype == torch.float16:
+        return GF_F16
+    raise TypeError("image must be float32 or float16")
+
+
+def _require_device(*ts):
+    dev = None
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("all tensors must be on the HIP device")
+        if not t.is_contiguous():
+            raise ValueError("all tensors must be contiguous")
+        dev = t.device if dev is None else dev
+        if t.device != dev:
+            raise ValueError("all tensors must be on the same device")
+    return dev
+
+
+@dataclass
+class FillResult:
+    out: torch.Tensor          # filled image(s)
+    shell: torch.Tensor        # int32 shell map(s)
+    stats: torch.Tensor        # int32 device stats (layout in include/guidefill.h)
+    order: torch.Tensor | None = None
+    shell_offsets: torch.Tensor | None = None
+    front_hist: torch.Tensor | None = None
+
+    def host_stats(self) -> dict:
+        return stats_fields(self.stats)
+
+
+def stats_fields(stats: torch.Tensor) -> dict:
+    s = stats.cpu().tolist()
+    B = (len(s) - STAT_FRAME0) // STAT_PER_FRAME
+    frames = [s[STAT_FRAME0 + STAT_PER_FRAME * f:STAT_FRAME0 + STAT_PER_FRAME * (f + 1)]
+              for f in range(B)]
+    return {
+        "K": s[STAT_SHELLS], "filled": s[STAT_FILLED], "hole": s[STAT_HOLE],
+        "unfilled": s[STAT_HOLE] - s[STAT_FILLED], "max_front": s[STAT_MAX_FRONT],
+        "label_errors": s[STAT_LABEL_ERR], "order_truncated": bool(s[STAT_ORDER_TRUNC]),
+        "frame_K": [fr[0] for fr in frames], "frame_filled": [fr[1] for fr in frames],
+        "frame_hole": [fr[2] for fr in frames],
+    }
+
+
+class Workspace:
+    """Reusable device workspace (grows on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = threading.local()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = getattr(_default_ws, "ws", None)
+    if ws is None:
+        ws = Workspace()
+        _default_ws.ws = ws
+    return ws.get(nbytes, device)
+
+
+def fill_batched(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
+                 params: Params | None = None, out: torch.Tensor | None = None,
+                 shell: torch.Tensor | None = None, record_order: bool = False,
+                 record_fronts: bool = False, kcap: int | None = None,
+                 workspace: torch.Tensor | None = None, **kw) -> FillResult:
+    """Fill B frames in one launch.  img: B x H x W x C (float32 or float16),
+    label: B x H x W uint8, guide: B x H x W x 2 float32.  `out` may be `img`
+    (in place).  Keyword arguments override fields of `params`."""
+    p = params or Params()
+    if kw:
+        p = Params(**{**p.__dict__, **kw})
+    dev = _require_device(img, label, guide, out, shell)
+    if img.dim() != 4 or label.dim() != 3 or guide.dim() != 4:
+        raise ValueError("expected img B x H x W x C, label B x H x W, guide B x H x W x 2")
+    B, H, W, C = img.shape
+    if tuple(label.shape) != (B, H, W) or tuple(guide.shape) != (B, H, W, 2):
+        raise ValueError("shape mismatch between img, label and guide")
+    if label.dtype != torch.uint8 or guide.dtype != torch.float32:
+        raise TypeError("label must be uint8 and guide float32")
+    lib = load()
+    if out is None:
+        out = torch.empty_like(img)
+    if shell is None:
+        shell = torch.empty((B, H, W), dtype=torch.int32, device=dev)
+    stats = torch.empty(STAT_FRAME0 + STAT_PER_FRAME * B, dtype=torch.int32, device=dev)
+    cp = p.c_struct()
+    dt = _dtype_code(img)
+    if kcap is None:
+        kcap = min(H * W, 1 << 16) + 1
+    order = offs = hist = None
+    if record_order:
+        order = torch.empty(B * H * W, dtype=torch.int32, device=dev)
+        offs = torch.zeros(kcap, dtype=torch.int32, device=dev)
+    if record_fronts:
+        hist = torch.zeros(kcap, dtype=torch.int32, device=dev)
+    nbytes = lib.gf_workspace_size(B, H, W, C, dt, ctypes.byref(cp))
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    rc = lib.gf_fill_batched(_ptr(img), _ptr(out), B, H, W, C, dt, _ptr(label), _ptr(guide),
+                             ctypes.byref(cp), _ptr(shell), _ptr(stats), _ptr(order), _ptr(offs),
+                             _ptr(hist), int(kcap), _ptr(ws), ws.numel(), _stream_ptr(dev))
+    _check(rc, "gf_fill_batched")
+    return FillResult(out, shell, stats, order, offs, hist)
+
+
+def fill(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
+         params: Params | None = None, out: torch.Tensor | None = None, **kw) -> FillResult:
+    """Fill one frame: img H x W x C, label H x W, guide H x W x 2."""
+    if out is not None:
+        out = out.unsqueeze(0)
+    r = fill_batched(img.unsqueeze(0), label.unsqueeze(0), guide.unsqueeze(0), params, out=out, **kw)
+    r.out = r.out[0]
+    r.shell = r.shell[0]
+    return r
+
+
+def fill_backward(grad_out: torch.Tensor, fwd: FillResult, label: torch.Tensor,
+                  guide: torch.Tensor, params: Params | None = None,
+                  K: int | None = None, **kw):
+    """dL/d img_in and dL/d guide of a fill recorded with record_order=True.
+    Shapes B x H x W x C / B x H x W x 2.  Returns (grad_img, grad_guide)."""
+    p = params or Params()
+    if kw:
+        p = Params(**{**p.__dict__, **kw})
+    if fwd.order is None:
+        raise ValueError("the forward must be run with record_order=True")
+    img_out = fwd.out
+    if img_out.dim() == 3:
+        img_out = img_out.unsqueeze(0)
+    shell = fwd.shell if fwd.shell.dim() == 3 else fwd.shell.unsqueeze(0)
+    if label.dim() == 2:
+        label, guide, grad_out = label.unsqueeze(0), guide.unsqueeze(0), grad_out.unsqueeze(0)
+    dev = _require_device(grad_out, img_out, label, guide, shell)
+    if grad_out.dtype != torch.float32:
+        raise TypeError("grad_out must be float32")
+    B, H, W, C = img_out.shape
+    lib = load()
+    if K is None:
+        K = int(fwd.stats[STAT_SHELLS].item())
+    if bool(fwd.stats[STAT_ORDER_TRUNC].item()):
+        raise RuntimeError("the forward's shell offsets were truncated (raise kcap)")
+    grad_img = torch.empty_like(grad_out)
+    grad_guide = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
+    cp = p.c_struct()
+    dt = _dtype_code(img_out)
+    nbytes = lib.gf_backward_workspace_size(B, H, W, C, dt, ctypes.byref(cp))
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    rc = lib.gf_fill_backward(_ptr(grad_out), _ptr(img_out), B, H, W, C, dt, _ptr(label),
+                              _ptr(guide), _ptr(shell), _ptr(fwd.order), _ptr(fwd.shell_offsets),
+                              int(K), ctypes.byref(cp), _ptr(grad_img), _ptr(grad_guide), _ptr(ws),
+                              ws.numel(), _stream_ptr(dev))
+    _check(rc, "gf_fill_backward")
+    return grad_img, grad_guide
+
+
+class GuidefillFn(torch.autograd.Function):
+    """u_out = fill(img, g = (cos theta, sin theta) on the hole); differentiable
+    w.r.t. img (float32) and theta (float32, B x H x W).  The shell order is
+    fixed by the forward and never altered by the backward."""
+
+    @staticmethod
+    def forward(ctx, img, theta, label, params: Params):
+        g = torch.stack([torch.cos(theta), torch.sin(theta)], dim=-1)
+        g = torch.where((label == 1).unsqueeze(-1), g, torch.zeros_like(g)).contiguous()
+        r = fill_batched(img.contiguous(), label, g, params, record_order=True)
+        ctx.save_for_backward(theta, label, g)
+        ctx.fwd = r
+        ctx.params = params
+        ctx.mark_non_differentiable(r.shell)
+        return r.out, r.shell
+
+    @staticmethod
+    def backward(ctx, grad_out, grad_shell):
+        theta, label, g = ctx.saved_tensors
+        gi, gg = fill_backward(grad_out.contiguous().float(), ctx.fwd, label, g, ctx.params)
+        gtheta = -torch.sin(theta) * gg[..., 0] + torch.cos(theta) * gg[..., 1]
+        return gi, gtheta, None, None

@@ -26,6 +26,7 @@ is (gx, gy) with gx along columns and gy along rows.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -378,18 +379,34 @@ def config3(seed: int = 3, H: int = 2160, W: int = 3840) -> Workload:
                     {"seed": seed, "H": H, "W": W})
 
 
-def config4(seed: int = 4, B: int = 64, H: int = 1080, W: int = 1920) -> Workload:
-    imgs, labels, guides, fracs = [], [], [], []
-    for f in range(B):
-        rng = np.random.default_rng([seed, f])
-        frac = float(np.clip(rng.lognormal(math.log(0.02), 0.5), 0.005, 0.08))
-        img, label, guide = _frame_c2(rng, H, W, target_fraction=frac)
-        imgs.append(img.astype(np.float16))
-        labels.append(label)
-        guides.append(guide)
-        fracs.append(frac)
-    return Workload("c4", np.stack(imgs), np.stack(labels), np.stack(guides), 3.0, 50.0,
-                    {"seed": seed, "B": B, "H": H, "W": W, "target_fractions": fracs})
+def _frame_c4(args):
+    seed, f, H, W = args
+    rng = np.random.default_rng([seed, f])
+    frac = float(np.clip(rng.lognormal(math.log(0.02), 0.5), 0.005, 0.08))
+    img, label, guide = _frame_c2(rng, H, W, target_fraction=frac)
+    return img.astype(np.float16), label, guide, frac
+
+
+def _map_frames(fn, jobs, workers):
+    if workers is None:
+        workers = min(len(jobs), os.cpu_count() or 1, 16)
+    if workers <= 1 or len(jobs) <= 1:
+        return [fn(j) for j in jobs]
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(fn, jobs)
+
+
+def config4(seed: int = 4, B: int = 64, H: int = 1080, W: int = 1920,
+            workers: int | None = None) -> Workload:
+    """Frame f is drawn from rng([seed, f]) alone, so any subset of frames
+    can be regenerated independently (frames=...)."""
+    res = _map_frames(_frame_c4, [(seed, f, H, W) for f in range(B)], workers)
+    return Workload("c4", np.stack([r[0] for r in res]), np.stack([r[1] for r in res]),
+                    np.stack([r[2] for r in res]), 3.0, 50.0,
+                    {"seed": seed, "B": B, "H": H, "W": W,
+                     "target_fractions": [r[3] for r in res]})
 
 
 def config5(seed: int = 5, B: int = 16, H: int = 512, W: int = 512):

@@ -1,0 +1,70 @@
+"""Helpers for the GPU tests: run the HIP path through the binding and compare
+with the oracle under the acceptance rules (shell map bit-exact; binary32
+colours within 1e-5 relative to max(|ref|, 1e-2); binary16 storage within one
+binary16 spacing)."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+
+def banner(msg: str):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def gpu_fill(img, label, guide, **kw):
+    """img: (B x) H x W x C numpy; returns (u float64 numpy, shell int32 numpy, stats dict, result)."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    batched = label.ndim == 3
+    if not batched:
+        img, label, guide = img[None], label[None], guide[None]
+    dtype = kw.pop("dtype", torch.float32)
+    record = kw.pop("record_order", False)
+    fronts = kw.pop("record_fronts", False)
+    inplace = kw.pop("inplace", False)
+    ti = to_dev(img).to(dtype)
+    tl = to_dev(label.astype(np.uint8))
+    tg = to_dev(guide.astype(np.float32))
+    out = ti if inplace else None
+    r = gf.fill_batched(ti, tl, tg, out=out, record_order=record, record_fronts=fronts, **kw)
+    torch.cuda.synchronize()
+    u = r.out.float().cpu().numpy().astype(np.float64)
+    s = r.shell.cpu().numpy()
+    st = r.host_stats()
+    if not batched:
+        u, s = u[0], s[0]
+    return u, s, st, r
+
+
+def assert_colour_parity(u_gpu, ref_u, shell, tol=1e-5):
+    filled = shell >= 0
+    if not filled.any():
+        return 0.0
+    a = u_gpu[filled]
+    b = ref_u[filled]
+    rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-2)
+    worst = float(rel.max())
+    assert worst <= tol, f"max relative colour error {worst:.3e} > {tol}"
+    return worst
+
+
+def f16_ulps(a, b):
+    """|a - b| in units of the binary16 spacing at b."""
+    b16 = b.astype(np.float16)
+    sp = np.spacing(np.abs(b16)).astype(np.float64)
+    return np.abs(a - b) / sp

@@ -1,0 +1,135 @@
+"""C ABI contract on the CPU: the library builds and loads, exports every
+function the header declares, and rejects bad arguments synchronously
+(argument checks run before any HIP call, so no device is needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "guidefill.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1611_05319_amd as gf
+    from paper_1611_05319_amd import build
+
+    if not os.path.exists(gf.library_path()):
+        build.build()
+    return gf.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(gf_[a-z_0-9]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for n in ("gf_fill", "gf_fill_batched", "gf_fill_backward", "gf_workspace_size",
+              "gf_backward_workspace_size", "gf_status_string", "gf_last_error", "gf_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in _declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_version_and_status_strings(lib):
+    assert lib.gf_version() == 1
+    assert lib.gf_status_string(0) == b"ok"
+    assert lib.gf_status_string(-1) == b"invalid argument"
+    assert lib.gf_status_string(-2) == b"HIP device error"
+    assert lib.gf_status_string(-3) == b"unsupported request"
+
+
+def test_workspace_size(lib):
+    import paper_1611_05319_amd as gf
+
+    p = gf.Params().c_struct()
+    n1 = lib.gf_workspace_size(1, 1080, 1920, 3, 0, ctypes.byref(p))
+    n2 = lib.gf_workspace_size(2, 1080, 1920, 3, 0, ctypes.byref(p))
+    assert n1 >= 2 * 1080 * 1920 * 4 and n2 > n1
+    assert n1 % 256 == 0
+    assert lib.gf_workspace_size(0, 10, 10, 3, 0, ctypes.byref(p)) == 0
+    assert lib.gf_backward_workspace_size(1, 10, 10, 3, 0, ctypes.byref(p)) >= 256
+
+
+def _call(lib, params, B=1, H=8, W=8, C=3, dt=0, ptr=1 << 20, ws_bytes=1 << 20, ws=1 << 20,
+          kcap=0, order=None, offs=None):
+    P = ctypes.c_void_p
+    fake = P(ptr)
+    return lib.gf_fill_batched(fake, fake, B, H, W, C, dt, fake, fake, ctypes.byref(params),
+                               fake, fake, order, offs, None, kcap, P(ws), ws_bytes, None)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("eps", 0.0), ("eps", 0.5), ("eps", 9.5), ("eps", float("nan")), ("mu", 0.0),
+    ("mu", -1.0), ("mu", float("inf")), ("c", float("nan")), ("max_shells", -1),
+    ("group", 16), ("blocks_per_cu", 9), ("blocks_per_cu", -1)])
+def test_bad_parameters_are_rejected(lib, field, value):
+    import paper_1611_05319_amd as gf
+
+    p = gf.Params()
+    setattr(p, field, value)
+    assert _call(lib, p.c_struct()) == -1
+
+
+@pytest.mark.parametrize("shape", [(0, 8, 8, 3), (1, 0, 8, 3), (1, 8, 0, 3), (1, 8, 8, 0),
+                                   (1, 8, 8, 5)])
+def test_bad_shapes_are_rejected(lib, shape):
+    import paper_1611_05319_amd as gf
+
+    B, H, W, C = shape
+    assert _call(lib, gf.Params().c_struct(), B=B, H=H, W=W, C=C) == -1
+
+
+def test_bad_pointers_and_workspace_are_rejected(lib):
+    import paper_1611_05319_amd as gf
+
+    p = gf.Params().c_struct()
+    assert _call(lib, p, ptr=0) == -1               # null device pointers
+    assert _call(lib, p, ws_bytes=16) == -1          # workspace too small
+    assert _call(lib, p, ws=(1 << 20) + 8) == -1     # misaligned workspace
+    assert _call(lib, p, dt=7) == -1                 # unknown dtype
+    # order_out without shell_offsets (and the reverse)
+    assert _call(lib, p, order=ctypes.c_void_p(1 << 20), kcap=4) == -1
+    assert _call(lib, p, offs=ctypes.c_void_p(1 << 20), kcap=4) == -1
+    # too many pixels for int32 list entries
+    big = gf.Params().c_struct()
+    assert _call(lib, big, B=1 << 12, H=1 << 10, W=1 << 10, ws_bytes=1 << 62) == -3
+
+
+def test_backward_rejects_bad_arguments(lib):
+    import paper_1611_05319_amd as gf
+
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    p = gf.Params().c_struct()
+    rc = lib.gf_fill_backward(fake, fake, 1, 8, 8, 3, 0, fake, fake, fake, None, fake, 2,
+                              ctypes.byref(p), fake, fake, fake, 1 << 20, None)
+    assert rc == -1
+    rc = lib.gf_fill_backward(fake, fake, 1, 8, 8, 3, 0, fake, fake, fake, fake, fake, -1,
+                              ctypes.byref(p), fake, fake, fake, 1 << 20, None)
+    assert rc == -1
+
+
+def test_python_binding_fails_loudly_without_device():
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    img = torch.zeros(4, 4, 3)
+    lab = torch.zeros(4, 4, dtype=torch.uint8)
+    g = torch.zeros(4, 4, 2)
+    with pytest.raises(ValueError):
+        gf.fill(img, lab, g)

@@ -1,0 +1,99 @@
+"""Reverse-shell adjoint on the GPU against the oracle's adjoint (which is
+itself pinned to FP64 finite differences and to the impulse matrix on the
+CPU).  Per-probe error <= 1e-4 and relative L2 error <= 1e-5."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+from gpu_helpers import banner, gpu_fill, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _frames(B, H, W, seed=5):
+    imgs, labs, thetas = [], [], []
+    for f in range(B):
+        rng = np.random.default_rng([seed, f])
+        imgs.append(syn.smooth_image(rng, H, W, 3, n_edges=12))
+        labs.append(syn.wiggly_bands(rng, H, W, 3, 6.0, 16.0))
+        thetas.append(syn.smooth_angle_field(rng, H, W))
+    lab = np.stack(labs)
+    th = np.stack(thetas)
+    g = np.stack([np.cos(th), np.sin(th)], -1).astype(np.float32)
+    g = np.where((lab == 1)[..., None], g, np.float32(0)).astype(np.float32)
+    return np.stack(imgs), lab, g, th
+
+
+def _compare(B, H, W, ghost=True, mu=50.0):
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    img, lab, g, th = _frames(B, H, W)
+    rng = np.random.default_rng(77)
+    omega = rng.normal(size=img.shape).astype(np.float32)
+    u, s, st, r = gpu_fill(img, lab, g, record_order=True, ghost=ghost, mu=mu)
+    gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g),
+                              gf.Params(eps=3.0, mu=mu, ghost=ghost))
+    torch.cuda.synchronize()
+    gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
+    ref = oracle.fill(img, lab, g, mu=mu, ghost=ghost)
+    np.testing.assert_array_equal(s, ref.shell)
+    # the oracle adjoint evaluated at the GPU's forward output (binary32 colours)
+    ri, rg = oracle.adjoint(lab, g, u, s, omega.astype(np.float64), mu=mu, ghost=ghost)
+    for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
+        err = np.abs(a - b)
+        rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        banner(f"grad {name}: max abs {err.max():.2e} rel L2 {rel_l2:.2e}")
+        assert err.max() <= 1e-4
+        assert rel_l2 <= 1e-5
+    return st
+
+
+@pytest.mark.parametrize("ghost", [True, False])
+def test_adjoint_small(ghost):
+    banner(f"adjoint 2 x 96 x 128 ghost={ghost}")
+    _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0)
+
+
+def test_adjoint_config5_full():
+    banner("adjoint 16 x 512 x 512")
+    st = _compare(16, 512, 512)
+    assert st["K"] >= 3
+
+
+def test_autograd_function():
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner("autograd function")
+    img, lab, g, th = _frames(2, 64, 80)
+    timg = to_dev(img).requires_grad_(True)
+    tth = to_dev(th).requires_grad_(True)
+    tlab = to_dev(lab)
+    out, shell = gf.GuidefillFn.apply(timg, tth, tlab, gf.Params(eps=3.0, mu=50.0))
+    rng = np.random.default_rng(3)
+    omega = to_dev(rng.normal(size=img.shape).astype(np.float32))
+    (out * omega).sum().backward()
+    # reference: oracle adjoint at the GPU forward, chained to theta
+    u = out.detach().cpu().numpy().astype(np.float64)
+    s = shell.cpu().numpy()
+    gnp = np.stack([np.cos(th), np.sin(th)], -1).astype(np.float32)
+    gnp = np.where((lab == 1)[..., None], gnp, np.float32(0))
+    ri, rg = oracle.adjoint(lab, gnp, u, s, omega.cpu().numpy().astype(np.float64))
+    rth = -np.sin(th) * rg[..., 0] + np.cos(th) * rg[..., 1]
+    rth = np.where(lab == 1, rth, 0.0)
+    assert np.abs(timg.grad.cpu().numpy() - ri).max() <= 1e-4
+    gth = tth.grad.cpu().numpy()
+    assert np.abs(np.where(lab == 1, gth, 0.0) - rth).max() <= 1e-4

@@ -1,0 +1,251 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Shell maps must be bit-exact; binary32 colours within 1e-5 relative
+(max(|ref|, 1e-2) floor); tracked and untracked forms, batched and single
+frames, in place and out of place must agree with each other exactly."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+from gpu_helpers import assert_colour_parity, banner, f16_ulps, gpu_fill
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1611_05319_amd as gf
+
+    gf.load()
+
+
+def _check(img, lab, g, eps=3.0, mu=50.0, c=-1.0, ghost=True, tracking=True, **kw):
+    ref = oracle.fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost)
+    u, s, st, _ = gpu_fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking, **kw)
+    np.testing.assert_array_equal(s, ref.shell)
+    worst = assert_colour_parity(u, ref.u, ref.shell)
+    # pixels that are not filled keep their input colour exactly
+    keep = ref.shell < 0
+    np.testing.assert_array_equal(u[keep], img[keep].astype(np.float64))
+    assert st["K"] == ref.K and st["filled"] == ref.n_filled and st["hole"] == ref.stats[0, 4]
+    return ref, u, s, st, worst
+
+
+def test_config1_tracked_and_untracked():
+    w = syn.config1()
+    for tracking in (True, False):
+        for ghost in (True, False):
+            banner(f"c1 tracking={tracking} ghost={ghost}")
+            _check(w.image[0], w.label[0], w.guide[0], ghost=ghost, tracking=tracking)
+
+
+CASES = [
+    # (H, W, C, eps, mu, c, ghost, p_hole, p_bys)
+    (1, 1, 3, 3.0, 50.0, -1.0, True, 0.5, 0.0),
+    (1, 23, 3, 3.0, 50.0, -1.0, True, 0.4, 0.1),
+    (29, 1, 1, 3.0, 50.0, -1.0, False, 0.4, 0.1),
+    (5, 7, 3, 3.0, 50.0, -1.0, True, 0.5, 0.1),
+    (33, 65, 3, 3.0, 50.0, -1.0, True, 0.35, 0.1),
+    (64, 64, 4, 2.0, 10.0, -1.0, True, 0.4, 0.05),
+    (97, 130, 3, 3.6, 20.0, -1.0, True, 0.3, 0.1),
+    (71, 90, 2, 5.0, 100.0, -1.0, True, 0.4, 0.1),
+    (71, 90, 3, 5.0, 100.0, -1.0, False, 0.4, 0.1),
+    (80, 77, 3, 3.0, 50.0, 0.05, True, 0.35, 0.1),
+    (80, 77, 1, 3.0, 5.0, 0.3, False, 0.35, 0.1),
+    (128, 256, 3, 3.0, 50.0, -1.0, True, 0.6, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}-e{c[3]}-c{c[5]}-g{int(c[6])}" for c in CASES])
+@pytest.mark.parametrize("tracking", [True, False])
+def test_random_problems(case, tracking):
+    H, W, C, eps, mu, c, ghost, ph, pb = case
+    banner(f"random {case} tracking={tracking}")
+    rng = np.random.default_rng(hash(case) % (1 << 32))
+    img, lab, g = syn.random_tiny(rng, H, W, C=C, p_hole=ph, p_bystander=pb,
+                                  blob=min(H, W) > 4)
+    ref = oracle.fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost)
+    if c >= 0:
+        assert ref.n_ties == 0, "confidence within the tie band of the threshold"
+    _check(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking)
+
+
+def test_lattice_line_angles():
+    # angles that put ghost points exactly on lattice lines (30, 45, 90 degrees)
+    rng = np.random.default_rng(3)
+    H, W = 60, 70
+    img, lab, g = syn.random_tiny(rng, H, W, C=3, p_hole=0.45, p_bystander=0.05)
+    angles = np.deg2rad(np.array([0.0, 30.0, 45.0, 60.0, 90.0, 150.0, 210.0, 270.0]))
+    pick = rng.integers(0, len(angles), size=(H, W))
+    g = np.stack([np.cos(angles[pick]), np.sin(angles[pick])], -1).astype(np.float32)
+    g = np.where((lab == 1)[..., None], g, np.float32(0))
+    for tracking in (True, False):
+        banner(f"lattice-line angles tracking={tracking}")
+        _check(img, lab, g, tracking=tracking)
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(8)
+    img = rng.uniform(0, 1, size=(40, 50, 3)).astype(np.float32)
+    g = np.zeros((40, 50, 2), np.float32)
+    g[..., 0] = 1.0
+    # no hole at all
+    banner("edge: no hole")
+    lab = np.zeros((40, 50), np.uint8)
+    ref, u, s, st, _ = _check(img, lab, g)
+    assert st["K"] == 0 and st["hole"] == 0
+    # everything is hole: nothing readable, nothing filled
+    banner("edge: all hole")
+    lab = np.ones((40, 50), np.uint8)
+    ref, u, s, st, _ = _check(img, lab, g)
+    assert (s == -3).all() and st["filled"] == 0
+    # hole surrounded by bystanders (stall), and a hole on the image border
+    banner("edge: stall")
+    lab = np.zeros((40, 50), np.uint8)
+    lab[10:30, 10:30] = 2
+    lab[15:25, 15:25] = 1
+    lab[0:3, 40:50] = 1
+    ref, u, s, st, _ = _check(img, lab, g)
+    assert (s[15:25, 15:25] == -3).all() and st["unfilled"] == 100
+    # label values outside {0, 1, 2} are counted and act as bystanders
+    banner("edge: bad labels")
+    lab = np.zeros((40, 50), np.uint8)
+    lab[5:12, 5:30] = 1
+    lab[20, 20] = 7
+    ref_lab = lab.copy()
+    ref_lab[20, 20] = 2
+    ref = oracle.fill(img, ref_lab, g)
+    u, s, st, _ = gpu_fill(img, lab, g)
+    np.testing.assert_array_equal(s, ref.shell)
+    assert st["label_errors"] == 1
+
+
+def test_constant_image_is_exact():
+    banner("constant image")
+    rng = np.random.default_rng(4)
+    img, lab, g = syn.random_tiny(rng, 90, 110, C=3, p_hole=0.4, p_bystander=0.1)
+    img[:] = np.array([0.25, 0.7, 1.0 / 3.0], np.float32)
+    u, s, _, _ = gpu_fill(img, lab, g)
+    filled = s >= 0
+    assert filled.sum() > 100
+    np.testing.assert_array_equal(u[filled], np.broadcast_to(img[0, 0].astype(np.float64),
+                                                            u[filled].shape))
+
+
+def test_forms_agree_exactly():
+    banner("forms: tracked/untracked, in place, groups, batched, repeat")
+    w = syn.config1(seed=11, H=200, W=240)
+    img, lab, g = w.image[0], w.label[0], w.guide[0]
+    u0, s0, st0, _ = gpu_fill(img, lab, g)
+    for kw in ({"tracking": False}, {"inplace": True}, {"group": 64}, {"blocks_per_cu": 1},
+               {"blocks_per_cu": 8}, {}):
+        u1, s1, st1, _ = gpu_fill(img, lab, g, **kw)
+        np.testing.assert_array_equal(s1, s0)
+        if "group" in kw:   # another reduction tree: FP64 sums differ in the last bits
+            assert np.abs(u1 - u0).max() <= 2.0 ** -23
+        else:
+            np.testing.assert_array_equal(u1, u0)
+        assert st1["K"] == st0["K"]
+    # batched frames give the per-frame results
+    rng = np.random.default_rng(12)
+    frames = [syn.random_tiny(rng, 64, 80, C=3, p_hole=p, p_bystander=0.05) for p in (0.1, 0.3, 0.6)]
+    bi = np.stack([f[0] for f in frames])
+    bl = np.stack([f[1] for f in frames])
+    bg = np.stack([f[2] for f in frames])
+    ub, sb, stb, _ = gpu_fill(bi, bl, bg)
+    for i, (fi, fl, fg) in enumerate(frames):
+        ui, si, sti, _ = gpu_fill(fi, fl, fg)
+        np.testing.assert_array_equal(sb[i], si)
+        np.testing.assert_array_equal(ub[i], ui)
+        assert stb["frame_K"][i] == sti["K"] and stb["frame_filled"][i] == sti["filled"]
+        assert stb["frame_hole"][i] == sti["hole"]
+
+
+def test_front_sizes_match_active_boundary():
+    # the tracked front of shell k is exactly the active boundary of D^(k)
+    banner("front sizes")
+    rng = np.random.default_rng(6)
+    img, lab, g = syn.random_tiny(rng, 120, 150, C=3, p_hole=0.5, p_bystander=0.08)
+    ref = oracle.fill(img, lab, g)
+    for tracking in (True, False):
+        u, s, st, r = gpu_fill(img, lab, g, tracking=tracking, record_fronts=True)
+        hist = r.front_hist.cpu().numpy()
+        K = ref.K
+        np.testing.assert_array_equal(hist[:K], ref.front_hist[0, :K])
+        assert st["max_front"] == ref.max_front
+
+
+def test_max_shells_resume():
+    banner("max_shells resume")
+    rng = np.random.default_rng(9)
+    img, lab, g = syn.random_tiny(rng, 100, 120, C=3, p_hole=0.5, p_bystander=0.05)
+    u_full, s_full, st_full, _ = gpu_fill(img, lab, g)
+    assert st_full["K"] >= 4
+    m = 3
+    u1, s1, st1, _ = gpu_fill(img, lab, g, max_shells=m)
+    assert st1["K"] == m
+    lab2 = lab.copy()
+    lab2[s1 >= 0] = 0
+    u2, s2, _, _ = gpu_fill(u1.astype(np.float32), lab2, g)
+    s = np.where(s2 >= 0, s2 + m, s1)
+    s = np.where((lab == 1) & (s1 >= 0), s1, s)
+    np.testing.assert_array_equal(s, s_full)
+    np.testing.assert_array_equal(u2, u_full)
+
+
+def test_fp16_storage():
+    import torch
+
+    banner("fp16 storage")
+    rng = np.random.default_rng(10)
+    img, lab, g = syn.random_tiny(rng, 150, 170, C=3, p_hole=0.4, p_bystander=0.05)
+    img16 = img.astype(np.float16)
+    ref = oracle.fill(img16.astype(np.float64), lab, g, storage="f16")
+    u, s, st, _ = gpu_fill(img16.astype(np.float32), lab, g, dtype=torch.float16)
+    np.testing.assert_array_equal(s, ref.shell)
+    filled = s >= 0
+    ulps = f16_ulps(u[filled], ref.u[filled])
+    assert ulps.max() <= 1.0, f"{ulps.max()} binary16 spacings"
+    assert (ulps > 0).mean() < 1e-3
+
+
+def test_config2_full_size():
+    w = syn.config2()
+    img, lab, g = w.image[0], w.label[0], w.guide[0]
+    for tracking in (True, False):
+        banner(f"c2 1920x1080 tracking={tracking}")
+        ref, u, s, st, worst = _check(img, lab, g, tracking=tracking)
+        banner(f"c2 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
+
+
+def test_config3_full_size():
+    w = syn.config3()
+    banner("c3 3840x2160 eps=5 mu=100")
+    ref, u, s, st, worst = _check(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0)
+    banner(f"c3 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
+    assert st["K"] > 50
+
+
+def test_config4_batched_sampled():
+    import torch
+
+    banner("c4 64 x 1920x1080 fp16 (generate)")
+    w = syn.config4()
+    banner("c4 fill")
+    u, s, st, _ = gpu_fill(w.image.astype(np.float32), w.label, w.guide, dtype=torch.float16)
+    for f in (0, 17, 42, 63):
+        banner(f"c4 frame {f} vs oracle")
+        ref = oracle.fill(w.image[f].astype(np.float64), w.label[f], w.guide[f], storage="f16")
+        np.testing.assert_array_equal(s[f], ref.shell)
+        filled = ref.shell >= 0
+        ulps = f16_ulps(u[f][filled], ref.u[filled])
+        assert ulps.max() <= 1.0
+        assert st["frame_K"][f] == ref.K and st["frame_filled"][f] == ref.n_filled
