@@ -1,0 +1,236 @@
+"""Benchmark of the MI355X shell fill (Guidefill, arXiv 1611.05319).
+
+A step is one complete fill (every shell, tracked front, out of place) of the
+1920x1080 RGB binary32 synthetic frame with eps = 3, mu = 50 (six silhouette
+bands 5-20 px wide, spline / structure-tensor guide).  Inputs are resident on
+the device before the timed region.  The JSON line reports Mpix filled per
+second, the fill call's algorithmic HBM bytes against the 8 TB/s peak, the
+FP64 CPU oracle on the host cores, and the side comparisons named by the
+metric: tracked vs untracked, one batched launch of 64 fp16 frames vs 64
+single-frame launches, forward vs forward + backward on 16 x 512 x 512.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --profile          (fill steps only, for rocprofv3 runs)
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synthetic as syn  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mpix filled/s + HBM GB/s fraction @1080p eps=3; batched vs plain; fwd+bwd ms"
+
+
+def algorithmic_bytes(B, H, W, C, elem, n_hole, inplace=False):
+    """Bytes the fill must move: image in and out, labels in, shell map out,
+    guide on hole pixels (8 B each)."""
+    px = B * H * W
+    if inplace:
+        return px * (1 + 4) + n_hole * (8 + 2 * C * elem)
+    return px * (C * elem + 1 + C * elem + 4) + n_hole * 8
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The FP64 oracle, as it stands, on the host cores, on repeated fills of
+    the same frame until ~budget_s of CPU time."""
+    import oracle
+
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+    img, lab, g = w.image[0], w.label[0], w.guide[0]
+    r = oracle.fill(img, lab, g, eps=w.eps, mu=w.mu, threads=threads)  # warm (build, page-in)
+    n = r.n_filled
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.fill(img, lab, g, eps=w.eps, mu=w.mu, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 1000:
+            break
+    return {"value": round(n * reps / el / 1e6, 4), "unit": "Mpix filled/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} complete FP64 fills of the 1920x1080 frame ({n} hole px each), "
+                      f"{el:.1f} s"}
+
+
+def time_steps(fn, steps, warmup, torch):
+    """Warm up, then time exactly `steps` calls: wall clock between two device
+    synchronisations, and per-call HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    ev_ms = [a.elapsed_time(b) for a, b in evs]
+    return wall_ms, float(np.mean(ev_ms)), float(np.median(ev_ms))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--profile", action="store_true", help="fill steps only (for rocprofv3)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=512, help="plain copy size in --profile mode")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (frames shard with no exchange; "
+              "see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    # ---- inputs (generated before the device is touched) ---------------------
+    w2 = syn.config2()
+    extras = not (args.no_extras or args.profile)
+    if extras:
+        w4 = syn.config4()
+        w5, theta5 = syn.config5()
+    base = None
+    if not (args.no_cpu_baseline or args.profile):
+        base = cpu_baseline(w2)
+
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    dev = torch.device("cuda:0")
+    B, H, W, C = w2.image.shape
+    img = torch.from_numpy(w2.image).to(dev)
+    lab = torch.from_numpy(w2.label).to(dev)
+    gd = torch.from_numpy(w2.guide).to(dev)
+    params = gf.Params(eps=w2.eps, mu=w2.mu)
+    plan = gf.FillPlan(img, lab, gd, params)
+    plan.run()
+    torch.cuda.synchronize()
+    st = gf.stats_fields(plan.stats)
+    n_filled = st["filled"]
+
+    if args.profile:
+        # a plain copy of known size, for scaling the HBM counters
+        nb = args.copy_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        wall, ev_mean, ev_med = time_steps(plan.run, args.steps, args.warmup, torch)
+        print(json.dumps({"profile": True, "steps": args.steps, "fill_event_ms": ev_mean,
+                          "copy_bytes": nb, "K": st["K"], "filled": n_filled}), flush=True)
+        return
+
+    wall, ev_mean, ev_med = time_steps(plan.run, args.steps, args.warmup, torch)
+    mpix = n_filled / (wall * 1e-3) / 1e6
+    nbytes = algorithmic_bytes(B, H, W, C, 4, st["hole"])
+    achieved = nbytes / (ev_mean * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(mpix, 3),
+        "unit": "Mpix filled/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain fill 1920x1080 RGB, binary32 storage, 6 silhouette bands "
+                               "5-20 px, spline/structure-tensor guide, eps=3, mu=50, onion "
+                               "order, ghost pixels, tracked front, out of place",
+                   "global_batch": 1, "hole_px": st["hole"], "filled_px": n_filled,
+                   "shells": st["K"], "max_front": st["max_front"], "parallelism": "none"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None,
+                     "algorithmic_bytes": nbytes, "event_ms_mean": round(ev_mean, 5),
+                     "event_ms_median": round(ev_med, 5),
+                     "us_per_shell": round(ev_mean * 1e3 / max(st["K"], 1), 3)},
+        "cpu_baseline": base,
+    }
+
+    if extras:
+        # tracked vs untracked (one lane per pixel per shell)
+        plan_u = gf.FillPlan(img, lab, gd, gf.Params(eps=w2.eps, mu=w2.mu, tracking=False))
+        wall_u, ev_u, _ = time_steps(plan_u.run, args.steps, args.warmup, torch)
+        out["untracked"] = {"ms_per_step": round(wall_u, 5), "event_ms": round(ev_u, 5),
+                            "value": round(n_filled / (wall_u * 1e-3) / 1e6, 3),
+                            "tracked_speedup": round(wall_u / wall, 3)}
+        # batched: 64 frames fp16, one launch vs 64 single-frame launches
+        i4 = torch.from_numpy(w4.image).to(dev)
+        l4 = torch.from_numpy(w4.label).to(dev)
+        g4 = torch.from_numpy(w4.guide).to(dev)
+        p4 = gf.Params(eps=w4.eps, mu=w4.mu)
+        plan_b = gf.FillPlan(i4, l4, g4, p4)
+        plans_1 = [gf.FillPlan(i4[f:f + 1], l4[f:f + 1], g4[f:f + 1], p4) for f in range(i4.shape[0])]
+        plan_b.run()
+        torch.cuda.synchronize()
+        st4 = gf.stats_fields(plan_b.stats)
+
+        def run_singles():
+            for pl in plans_1:
+                pl.run()
+
+        steps4 = max(3, args.steps // 10)
+        wall_b, ev_b, _ = time_steps(plan_b.run, steps4, 2, torch)
+        wall_s, ev_s, _ = time_steps(run_singles, steps4, 1, torch)
+        nb4 = algorithmic_bytes(*i4.shape, 2, st4["hole"])
+        out["batched"] = {"workload": "64 x 1920x1080 RGB fp16 storage, lognormal hole fraction "
+                                      "(median 2%), eps=3, mu=50",
+                          "hole_px": st4["hole"], "max_frame_shells": max(st4["frame_K"]),
+                          "batched_ms": round(wall_b, 4), "plain_64_launches_ms": round(wall_s, 4),
+                          "batched_speedup": round(wall_s / wall_b, 3),
+                          "mpix_filled_per_s": round(st4["filled"] / (wall_b * 1e-3) / 1e6, 2),
+                          "hbm_gbs": round(nb4 / (ev_b * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(nb4 / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del i4, l4, g4, plan_b, plans_1
+        # forward vs forward + backward (reverse-shell adjoint)
+        i5 = torch.from_numpy(w5.image).to(dev)
+        l5 = torch.from_numpy(w5.label).to(dev)
+        g5 = torch.from_numpy(w5.guide).to(dev)
+        p5 = gf.Params(eps=w5.eps, mu=w5.mu)
+        plan_f = gf.FillPlan(i5, l5, g5, p5, record_order=True)
+        plan_f.run()
+        torch.cuda.synchronize()
+        K5 = int(plan_f.stats[0].item())
+        grad = torch.randn_like(i5)
+        gi = torch.empty_like(i5)
+        gg = torch.empty(i5.shape[:3] + (2,), dtype=torch.float32, device=dev)
+        bw = gf.BackwardPlan(plan_f, grad, gi, gg, K5)
+
+        def fwd_bwd():
+            plan_f.run()
+            bw.run()
+
+        steps5 = max(5, args.steps // 5)
+        wall_f, _, _ = time_steps(plan_f.run, steps5, 2, torch)
+        wall_fb, _, _ = time_steps(fwd_bwd, steps5, 2, torch)
+        out["fwd_bwd"] = {"workload": "16 x 512x512 RGB fp32, band masks 6-16 px, smooth angle "
+                                      "field, eps=3, mu=50",
+                          "fwd_ms": round(wall_f, 4), "fwd_bwd_ms": round(wall_fb, 4),
+                          "ratio": round(wall_fb / wall_f, 3), "shells": K5}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

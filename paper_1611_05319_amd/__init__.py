@@ -23,7 +23,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Params", "FillResult", "fill", "fill_batched", "fill_backward", "GuidefillFn",
+    "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_backward", "GuidefillFn",
     "library_path", "load", "stats_fields",
 ]
 
@@ -281,6 +281,78 @@ def fill_backward(grad_out: torch.Tensor, fwd: FillResult, label: torch.Tensor,
                               ws.numel(), _stream_ptr(dev))
     _check(rc, "gf_fill_backward")
     return grad_img, grad_guide
+
+
+class FillPlan:
+    """Preallocated outputs and workspace for repeated fills of one shape:
+    `run()` is a single call into the library (no allocation, no sync)."""
+
+    def __init__(self, img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
+                 params: Params | None = None, inplace: bool = False, record_order: bool = False,
+                 kcap: int | None = None):
+        self.params = params or Params()
+        dev = _require_device(img, label, guide)
+        if img.dim() == 3:
+            img, label, guide = img.unsqueeze(0), label.unsqueeze(0), guide.unsqueeze(0)
+        B, H, W, C = img.shape
+        self.shape = (B, H, W, C)
+        self.img, self.label, self.guide = img, label, guide
+        self.out = img if inplace else torch.empty_like(img)
+        self.shell = torch.empty((B, H, W), dtype=torch.int32, device=dev)
+        self.stats = torch.empty(STAT_FRAME0 + STAT_PER_FRAME * B, dtype=torch.int32, device=dev)
+        self.kcap = kcap or (min(H * W, 1 << 16) + 1)
+        self.order = self.offsets = None
+        if record_order:
+            self.order = torch.empty(B * H * W, dtype=torch.int32, device=dev)
+            self.offsets = torch.zeros(self.kcap, dtype=torch.int32, device=dev)
+        self._cp = self.params.c_struct()
+        self._dt = _dtype_code(img)
+        lib = load()
+        nbytes = lib.gf_workspace_size(B, H, W, C, self._dt, ctypes.byref(self._cp))
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        self._lib = lib
+        self._args = (_ptr(img), _ptr(self.out), B, H, W, C, self._dt, _ptr(label), _ptr(guide),
+                      ctypes.byref(self._cp), _ptr(self.shell), _ptr(self.stats),
+                      _ptr(self.order), _ptr(self.offsets), None, int(self.kcap),
+                      _ptr(self.ws), self.ws.numel())
+        self.device = dev
+
+    def run(self, stream: torch.cuda.Stream | None = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rc = self._lib.gf_fill_batched(*self._args, ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            _check(rc, "gf_fill_batched")
+
+    def result(self) -> FillResult:
+        return FillResult(self.out, self.shell, self.stats, self.order, self.offsets, None)
+
+
+class BackwardPlan:
+    """Preallocated reverse-shell call for a FillPlan made with record_order=True:
+    grad_out -> (grad_img, grad_guide) with the forward's shell count K."""
+
+    def __init__(self, fwd: FillPlan, grad_out: torch.Tensor, grad_img: torch.Tensor,
+                 grad_guide: torch.Tensor, K: int):
+        if fwd.order is None:
+            raise ValueError("the forward plan must record the fill order")
+        _require_device(grad_out, grad_img, grad_guide)
+        B, H, W, C = fwd.shape
+        lib = load()
+        self._cp = fwd.params.c_struct()
+        nbytes = lib.gf_backward_workspace_size(B, H, W, C, fwd._dt, ctypes.byref(self._cp))
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=fwd.device)
+        self._lib = lib
+        self._args = (_ptr(grad_out), _ptr(fwd.out), B, H, W, C, fwd._dt, _ptr(fwd.label),
+                      _ptr(fwd.guide), _ptr(fwd.shell), _ptr(fwd.order), _ptr(fwd.offsets), int(K),
+                      ctypes.byref(self._cp), _ptr(grad_img), _ptr(grad_guide), _ptr(self.ws),
+                      self.ws.numel())
+        self.device = fwd.device
+
+    def run(self, stream: torch.cuda.Stream | None = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rc = self._lib.gf_fill_backward(*self._args, ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            _check(rc, "gf_fill_backward")
 
 
 class GuidefillFn(torch.autograd.Function):

@@ -193,23 +193,31 @@ __device__ inline bool readable(int32_t s, int k) {
 // grid barrier (all workgroups co-resident: cooperative launch)
 
 __device__ void grid_sync(int32_t *ctl, unsigned nblocks) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Waves of a workgroup share the CU's path to L2, so a workgroup-scope
+    // release plus one agent-scope release (L2 write-back) by thread 0 makes
+    // the whole workgroup's stores visible; thread 0 spins with relaxed loads
+    // (an acquire load would invalidate the caches on every iteration) and
+    // acquires once when the generation moves.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned *cnt = (unsigned *)&ctl[CTL_BAR_COUNT];
         unsigned *gen = (unsigned *)&ctl[CTL_BAR_GEN];
-        unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // orders the load above, too
+        const unsigned prev =
+            __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nblocks - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ inline int ld_ctl(const int32_t *ctl, int i) {
