@@ -51,15 +51,24 @@ typedef enum {
 
 typedef enum { GF_F32 = 0, GF_F16 = 1 } gf_dtype;
 
+typedef enum {
+    GF_ENGINE_TILED = 0, /* tile windows staged in LDS run pass_shells shells between grid syncs */
+    GF_ENGINE_FRONT = 1  /* one grid sync per shell; the front kept as one global list */
+} gf_engine;
+
 typedef struct {
-    double eps;         /* radius of the ball in pixels, 1 <= eps <= 9 (Sec. 3.1) */
-    double mu;          /* anisotropy of the weights, mu > 0 (eqn:weight) */
-    double c;           /* < 0: onion order; >= 0: smart order threshold (eqn:ready) */
-    int32_t ghost;      /* 1: rotated ball with ghost pixels; 0: lattice ball */
-    int32_t tracking;   /* 1: lanes for the tracked front only; 0: one lane per pixel per shell */
-    int32_t max_shells; /* 0: run until no pixel is ready; n > 0: stop after n shells */
-    int32_t group;      /* lanes cooperating on one pixel: 0 (auto), 32 or 64 */
+    double eps;          /* radius of the ball in pixels, 1 <= eps <= 9 (Sec. 3.1) */
+    double mu;           /* anisotropy of the weights, mu > 0 (eqn:weight) */
+    double c;            /* < 0: onion order; >= 0: smart order threshold (eqn:ready) */
+    int32_t ghost;       /* 1: rotated ball with ghost pixels; 0: lattice ball */
+    int32_t tracking;    /* 1: lanes for the tracked front only; 0: one lane per pixel per shell */
+    int32_t max_shells;  /* 0: run until no pixel is ready; n > 0: stop after n shells */
+    int32_t engine;      /* gf_engine */
+    int32_t group;       /* lanes per pixel: 0 (auto), 8 (tiled engine), 16, 32 or 64 */
     int32_t blocks_per_cu; /* persistent workgroups per compute unit: 0 (auto) or 1..8 */
+    int32_t tile_w, tile_h; /* tiled engine: tile interior in pixels, 0 = auto (<= 256) */
+    int32_t pass_shells;    /* tiled engine: shells per grid sync, 0 = auto (<= 32); the halo
+                               pass_shells * ceil(eps) may not exceed tile_w or tile_h */
     int32_t reserved;
 } gf_params;
 
@@ -92,12 +101,16 @@ size_t gf_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_param
  *   label, guide, shell_out: as above; shell_out is required.
  *   stats       int32[8 + 4*B], required.
  *   order_out   nullable; int32[B*H*W]: frame*H*W + pixel of every filled
- *               pixel, grouped by shell (the input of gf_fill_backward).
+ *               pixel, grouped by shell (the input of gf_fill_backward);
+ *               needs engine GF_ENGINE_FRONT (else GF_EUNSUPPORTED).
  *   shell_offsets nullable (required with order_out); int32[kcap]: entry k is
  *               the start of shell k in order_out, entry K its end.  If
  *               K + 1 > kcap the fill still completes and
  *               stats[GF_STAT_ORDER_TRUNC] is set.
- *   front_hist  nullable; int32[kcap]: active front size of each shell.
+ *   front_hist  nullable; int32[kcap]: active front size of each shell (the
+ *               tiled engine counts the active pixels of the tiles it visits;
+ *               pixels waiting in tiles whose neighbourhood did not change are
+ *               not recounted).
  *   workspace   >= gf_workspace_size(...) bytes.
  * Returns GF_OK or GF_EINVAL / GF_EUNSUPPORTED / GF_EDEVICE.
  */
@@ -138,6 +151,13 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
 
 /* Bytes of workspace gf_fill_backward needs. */
 size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
+
+/*
+ * Tile geometry the tiled engine would use for these parameters on the
+ * current device: out6 = {tile_w, tile_h, pass_shells, halo, LDS bytes of the
+ * window, lanes per pixel}.  Returns GF_EINVAL if no window fits.
+ */
+gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p, int32_t *out6);
 
 /* Text for a status code (static storage). */
 const char *gf_status_string(gf_status s);

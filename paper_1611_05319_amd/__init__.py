@@ -24,7 +24,7 @@ import torch
 
 __all__ = [
     "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_backward", "GuidefillFn",
-    "library_path", "load", "stats_fields",
+    "library_path", "load", "stats_fields", "tile_geometry", "ENGINE_TILED", "ENGINE_FRONT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,16 +38,23 @@ STAT_SHELLS, STAT_FILLED, STAT_HOLE, STAT_MAX_FRONT, STAT_LABEL_ERR, STAT_ORDER_
 STAT_FRAME0, STAT_PER_FRAME = 8, 4
 
 
+ENGINE_TILED, ENGINE_FRONT = 0, 1
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("mu", ctypes.c_double), ("c", ctypes.c_double),
                 ("ghost", ctypes.c_int32), ("tracking", ctypes.c_int32),
-                ("max_shells", ctypes.c_int32), ("group", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_shells", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("pass_shells", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 @dataclass
 class Params:
-    """Fill parameters (gf_params).  c < 0: onion order; c >= 0: smart order."""
+    """Fill parameters (gf_params).  c < 0: onion order; c >= 0: smart order.
+    engine 0: tiled (LDS windows, pass_shells shells per grid sync);
+    engine 1: one grid sync per shell with a global front list."""
 
     eps: float = 3.0
     mu: float = 50.0
@@ -55,13 +62,18 @@ class Params:
     ghost: bool = True
     tracking: bool = True
     max_shells: int = 0
+    engine: int = ENGINE_TILED
     group: int = 0
     blocks_per_cu: int = 0
+    tile_w: int = 0
+    tile_h: int = 0
+    pass_shells: int = 0
 
     def c_struct(self) -> _Params:
         return _Params(float(self.eps), float(self.mu), float(self.c), int(bool(self.ghost)),
-                       int(bool(self.tracking)), int(self.max_shells), int(self.group),
-                       int(self.blocks_per_cu), 0)
+                       int(bool(self.tracking)), int(self.max_shells), int(self.engine),
+                       int(self.group), int(self.blocks_per_cu), int(self.tile_w),
+                       int(self.tile_h), int(self.pass_shells), 0)
 
 
 def library_path() -> str:
@@ -96,6 +108,8 @@ def load():
         lib.gf_last_error.restype = ctypes.c_char_p
         lib.gf_version.argtypes = []
         lib.gf_version.restype = I
+        lib.gf_tile_geometry.argtypes = [I, I, I, I, PP, P]
+        lib.gf_tile_geometry.restype = I
         _lib = lib
         return lib
 
@@ -150,6 +164,18 @@ class FillResult:
 
     def host_stats(self) -> dict:
         return stats_fields(self.stats)
+
+
+def tile_geometry(H: int, W: int, C: int, dtype=torch.float32, params: Params | None = None):
+    """(tile_w, tile_h, pass_shells, halo, window LDS bytes, lanes per pixel) the
+    tiled engine uses for these parameters on the current device."""
+    lib = load()
+    p = (params or Params()).c_struct()
+    out = (ctypes.c_int32 * 6)()
+    rc = lib.gf_tile_geometry(H, W, C, GF_F16 if dtype == torch.float16 else GF_F32,
+                              ctypes.byref(p), out)
+    _check(rc, "gf_tile_geometry")
+    return tuple(out)
 
 
 def stats_fields(stats: torch.Tensor) -> dict:
@@ -209,6 +235,8 @@ def fill_batched(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
     if label.dtype != torch.uint8 or guide.dtype != torch.float32:
         raise TypeError("label must be uint8 and guide float32")
     lib = load()
+    if record_order and p.engine != ENGINE_FRONT:
+        p = Params(**{**p.__dict__, "engine": ENGINE_FRONT})  # the fill order comes from that engine
     if out is None:
         out = torch.empty_like(img)
     if shell is None:
@@ -291,6 +319,8 @@ class FillPlan:
                  params: Params | None = None, inplace: bool = False, record_order: bool = False,
                  kcap: int | None = None):
         self.params = params or Params()
+        if record_order and self.params.engine != ENGINE_FRONT:
+            self.params = Params(**{**self.params.__dict__, "engine": ENGINE_FRONT})
         dev = _require_device(img, label, guide)
         if img.dim() == 3:
             img, label, guide = img.unsqueeze(0), label.unsqueeze(0), guide.unsqueeze(0)

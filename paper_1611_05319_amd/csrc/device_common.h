@@ -1,0 +1,245 @@
+// Device helpers shared by the kernels of guidefill.hip: constants, control
+// words, storage conversions, group reductions, the grid barrier, the ball
+// offsets and the ghost-point geometry (Guidefill, arXiv 1611.05319, Sec. 3.1
+// and 3.3).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace gfk {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
+constexpr int kMaxOffsets = 256;  // eps <= 9: 252 offsets
+constexpr int kPerLaneMax = 4;    // ball offsets handled by one lane
+constexpr int kStageCap = 2048;   // LDS staging entries per workgroup
+constexpr int kFrameCap = 64;     // frames with LDS statistics accumulators (global engine)
+constexpr int kXcd = 8;           // XCDs of the MI355X; workgroups are dealt round robin
+constexpr int kCtlWords = 1024;   // control block (int32) at the start of the workspace
+
+// Control words.  Counters updated by many workgroups are split per XCD and
+// kept on separate 128-byte lines: same-address device atomics serialise.
+constexpr int kXStride = 32;
+enum : int {
+    XF_BAR = 0,     // barrier arrivals of this XCD's workgroups
+    XF_ACT = 1,     // [3] active-tile list lengths (tiled engine), ring by pass
+    XF_PFILL = 4,   // [3] pixels filled in the pass, ring by pass
+    XF_KMAX = 7,    // largest shell + 1 filled so far
+    XF_HOLE = 8,    // label-1 pixels
+    XF_ERR = 9,     // label errors
+};
+enum : int {
+    G_GEN = 256,    // barrier generation
+    G_TOP = 288,    // barrier arrivals of XCD groups
+    G_LIST = 320,   // [3] front-list lengths (global engine), ring by shell
+    G_FILL = 352,   // [3] pixels filled in the shell (global engine)
+    G_ACTIVE = 384, // [3] active pixels (global engine, untracked)
+    G_HOLE = 416,
+    G_ERR = 448,
+    G_ORDER = 480,  // entries written to order_out
+};
+__device__ inline int xw(int x, int field) { return x * kXStride + field; }
+
+// shell-map and window codes
+constexpr int32_t S_READABLE = -1;
+constexpr int32_t S_BYSTANDER = -2;
+constexpr int32_t S_UNFILLED = -3;
+constexpr int32_t S_HOLE = -4;   // in D, not on a front list
+constexpr int32_t S_FRONT = -5;  // in D, on the next front list
+
+// ---------------------------------------------------------------------------
+// storage types: arithmetic is FP64, storage binary32 or binary16
+
+template <typename TS> __device__ inline double load_px(const TS *p);
+template <> __device__ inline double load_px<float>(const float *p) { return (double)*p; }
+template <> __device__ inline double load_px<__half>(const __half *p) {
+    return (double)__half2float(*p);
+}
+
+// binary16 round to nearest even straight from binary64 (no double rounding
+// through binary32): keep 11 significant bits, round on the dropped ones.
+__device__ inline unsigned short f64_to_f16_bits(double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    unsigned short sign = (unsigned short)((b >> 48) & 0x8000u);
+    int e = (int)((b >> 52) & 0x7ff);
+    unsigned long long man = b & 0xFFFFFFFFFFFFFull;
+    if (e == 0x7ff) return (unsigned short)(sign | 0x7c00u | (man ? 0x200u : 0u));
+    if (e == 0) return sign;  // binary64 subnormals are far below binary16's range
+    int E = e - 1023;
+    if (E > 15) return (unsigned short)(sign | 0x7c00u);
+    unsigned long long full = man | (1ull << 52);
+    int shift;
+    unsigned hexp;
+    if (E >= -14) {
+        shift = 42;
+        hexp = (unsigned)(E + 15);
+    } else {
+        shift = 42 + (-14 - E);
+        hexp = 0;
+        if (shift > 63) return sign;
+    }
+    unsigned long long q = full >> shift;
+    unsigned long long rem = full & ((1ull << shift) - 1);
+    unsigned long long halfway = 1ull << (shift - 1);
+    if (rem > halfway || (rem == halfway && (q & 1ull))) ++q;
+    unsigned bits = hexp ? ((hexp << 10) + (unsigned)(q - 1024)) : (unsigned)q;
+    if (bits >= 0x7c00u) bits = 0x7c00u;
+    return (unsigned short)(sign | bits);
+}
+
+template <typename TS> __device__ inline TS to_storage(double v);
+template <> __device__ inline float to_storage<float>(double v) { return (float)v; }
+template <> __device__ inline __half to_storage<__half>(double v) {
+    return __ushort_as_half(f64_to_f16_bits(v));
+}
+
+// ---------------------------------------------------------------------------
+// group (G lanes) reductions
+
+template <int G> __device__ inline double gsum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+template <int G> __device__ inline double gmin(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+    return v;
+}
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
+
+// readable at shell k: -1 (readable from the start) or filled in a shell < k
+__device__ inline bool readable(int32_t s, int k) { return (unsigned)(s + 1) <= (unsigned)k; }
+
+// ---------------------------------------------------------------------------
+// grid barrier (all workgroups co-resident: cooperative launch).  Arrivals are
+// counted per XCD group first, then per group, so no counter sees more than
+// max(nblocks / 8, 8) serialised atomics.  Waves of a workgroup share the
+// CU's path to L2, so a workgroup-scope release plus one agent-scope release
+// (L2 write-back) by thread 0 publishes the workgroup's stores; waiting is a
+// relaxed spin (an acquire load would invalidate the caches on every
+// iteration) followed by one acquire.
+
+__device__ void grid_sync(int32_t *ctl, unsigned nblocks) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned x = blockIdx.x % kXcd;
+        const unsigned per_group = nblocks / kXcd;  // nblocks is a multiple of kXcd
+        unsigned *gen = (unsigned *)&ctl[G_GEN];
+        unsigned *top = (unsigned *)&ctl[G_TOP];
+        unsigned *grp = (unsigned *)&ctl[xw((int)x, XF_BAR)];
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // also orders the load above
+        const unsigned a = __hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if (a == per_group - 1) {
+            // the reset must be published before the group arrives at the top
+            __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const unsigned b =
+                __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = (b == kXcd - 1);
+        }
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+__device__ inline int ld_ctl(const int32_t *ctl, int i) {
+    return __hip_atomic_load(&ctl[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int sum_x(const int32_t *ctl, int field) {
+    int s = 0;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) s += ld_ctl(ctl, xw(x, field));
+    return s;
+}
+
+__device__ inline int max_x(const int32_t *ctl, int field) {
+    int s = 0;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) s = max(s, ld_ctl(ctl, xw(x, field)));
+    return s;
+}
+
+// logical workgroup id: consecutive logical ids share an XCD, so contiguous
+// ranges of pixels / list entries stay in one L2
+__device__ inline int logical_block() {
+    int n = (int)gridDim.x;
+    int b = (int)blockIdx.x;
+    return (b % kXcd) * (n / kXcd) + b / kXcd;
+}
+
+// ball offsets {(n, m): 0 < n^2 + m^2 <= eps^2}, m ascending then n, and the
+// reciprocal distances 1/|(n, m)| (the rotation preserves them)
+__device__ void build_offsets(double eps, short2 *off, double *rinv, int *T) {
+    if (threadIdx.x == 0) {
+        int R = (int)floor(eps);
+        int cnt = 0;
+        for (int m = -R; m <= R; ++m)
+            for (int n = -R; n <= R; ++n) {
+                int r2 = n * n + m * m;
+                if (r2 == 0 || (double)r2 > eps * eps) continue;
+                if (cnt < kMaxOffsets) {
+                    off[cnt] = make_short2((short)n, (short)m);
+                    rinv[cnt] = 1.0 / sqrt((double)r2);
+                }
+                ++cnt;
+            }
+        *T = cnt < kMaxOffsets ? cnt : kMaxOffsets;
+    }
+}
+
+// rotated offset R(n, m), R taking (0, 1) to g/|g| (Sec. 3.1), evaluated as
+// ox = n*s + m*c, oy = m*s - n*c with no fused operations
+__device__ inline void rot_offset(bool rot, double cs, double sn, int n, int m, double &ox,
+                                  double &oy) {
+    if (rot) {
+        double a = (double)n * sn;
+        double b = (double)m * cs;
+        double d = (double)m * sn;
+        double e = (double)n * cs;
+        ox = a + b;
+        oy = d - e;
+    } else {
+        ox = (double)n;
+        oy = (double)m;
+    }
+}
+
+// bilinear support of a ghost point at offset (ox, oy) from (X, Y): the pixels
+// with a nonzero basis value (|q - p|_inf < 1, eqn:bilinearDef)
+struct Support {
+    int x0, x1, y0, y1;  // x1 == x0 / y1 == y0 on a lattice line
+    double wx0, wx1, wy0, wy1;
+};
+
+__device__ inline Support support_of(int X, int Y, double ox, double oy) {
+    Support s;
+    double fx = floor(ox), fy = floor(oy);
+    bool ex = (ox == fx), ey = (oy == fy);
+    s.x0 = X + (int)fx;
+    s.y0 = Y + (int)fy;
+    s.x1 = s.x0 + (ex ? 0 : 1);
+    s.y1 = s.y0 + (ey ? 0 : 1);
+    if (ex) { s.wx0 = 1.0; s.wx1 = 0.0; } else { double f = ox - fx; s.wx0 = 1.0 - f; s.wx1 = f; }
+    if (ey) { s.wy0 = 1.0; s.wy1 = 0.0; } else { double f = oy - fy; s.wy0 = 1.0 - f; s.wy1 = f; }
+    return s;
+}
+
+}  // namespace gfk

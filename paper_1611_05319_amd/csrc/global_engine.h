@@ -1,0 +1,550 @@
+// Global-front engine: one cooperative persistent launch, a grid barrier
+// between shells, the front kept as a global list (tracked form) or found by
+// one lane per pixel per shell (untracked form); Guidefill, arXiv 1611.05319,
+// Algorithm 1 and Sec. 3.5.  Also the reverse-shell adjoint over a recorded
+// fill order.
+#pragma once
+
+#include "fill_core.h"
+
+namespace gfk {
+
+struct FillArgs {
+    const void *in;
+    void *out;
+    const uint8_t *label;
+    const float *guide;
+    int32_t *shell;
+    int32_t *stats;
+    int32_t *order;
+    int32_t *shell_off;
+    int32_t *front_hist;
+    int32_t *listA;
+    int32_t *listB;
+    int32_t *ctl;
+    long long HW;
+    long long NP;  // B * H * W
+    int B, H, W, C;
+    int kcap;
+    int tracking;
+    int max_shells;
+    int inplace;
+    double eps;
+    double a;  // mu^2 / (2 eps^2)
+    double c;  // < 0 onion
+    int ghost;
+};
+
+// LDS staging of list appends: one global atomic per workgroup per flush
+struct Stage {
+    int *buf;
+    int *n;
+};
+
+__device__ inline void stage_push(Stage st, int v, int32_t *glist, int32_t *gcount) {
+    int slot = atomicAdd(st.n, 1);
+    if (slot < kStageCap) {
+        st.buf[slot] = v;
+    } else {  // LDS full: append directly
+        int pos = atomicAdd(gcount, 1);
+        glist[pos] = v;
+    }
+}
+
+__device__ inline void stage_flush(Stage st, int32_t *glist, int32_t *gcount, int *s_base) {
+    __syncthreads();
+    int n = *st.n;
+    if (n > kStageCap) n = kStageCap;
+    if (threadIdx.x == 0) *s_base = n ? atomicAdd(gcount, n) : 0;
+    __syncthreads();
+    const int base = *s_base;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) glist[base + i] = st.buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *st.n = 0;
+}
+
+// bulk copy of bytes [b0, b1) with 16-byte lanes where both buffers allow,
+// four lanes in flight per thread
+__device__ inline void copy_range(const char *src, char *dst, size_t b0, size_t b1) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    size_t v0 = (b0 + 15) & ~(size_t)15, v1 = b1 & ~(size_t)15;
+    if (v0 > v1 || (((uintptr_t)src | (uintptr_t)dst) & 15) != 0) v0 = v1 = b0;
+    for (size_t i = b0 + tid; i < v0; i += nt) dst[i] = src[i];
+    const size_t step = (size_t)nt * 16;
+    size_t i = v0 + (size_t)tid * 16;
+    for (; i + 3 * step < v1; i += 4 * step) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(src + i);
+        const uint4 b = *reinterpret_cast<const uint4 *>(src + i + step);
+        const uint4 c = *reinterpret_cast<const uint4 *>(src + i + 2 * step);
+        const uint4 d = *reinterpret_cast<const uint4 *>(src + i + 3 * step);
+        *reinterpret_cast<uint4 *>(dst + i) = a;
+        *reinterpret_cast<uint4 *>(dst + i + step) = b;
+        *reinterpret_cast<uint4 *>(dst + i + 2 * step) = c;
+        *reinterpret_cast<uint4 *>(dst + i + 3 * step) = d;
+    }
+    for (; i < v1; i += step)
+        *reinterpret_cast<uint4 *>(dst + i) = *reinterpret_cast<const uint4 *>(src + i);
+    for (size_t j = (v1 > b0 ? v1 : b0) + tid; j < b1; j += nt) dst[j] = src[j];
+}
+
+template <typename TS, int G>
+__device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const double *rinv, int T,
+                                  long long gidx, int k, int l) {
+    const long long f = gidx / A.HW;
+    const int p = (int)(gidx - f * A.HW);
+    const int Y = p / A.W, X = p - Y * A.W;
+    GlobalView<TS> v{A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
+                     A.W, A.H, A.C};
+    const float2 gv = reinterpret_cast<const float2 *>(A.guide)[gidx];
+    double val[4];
+    if (!fill_core<TS, G>(v, X, Y, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T, k, l,
+                          A.a, A.c, val))
+        return false;
+    if (l == 0) {
+        TS *o = reinterpret_cast<TS *>(A.out) + gidx * A.C;
+        for (int ch = 0; ch < A.C; ++ch) o[ch] = to_storage<TS>(val[ch]);
+        A.shell[gidx] = k;
+    }
+    return true;
+}
+
+template <typename TS, int G>
+__global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
+    __shared__ short2 s_off[kMaxOffsets];
+    __shared__ double s_rinv[kMaxOffsets];
+    __shared__ int s_T;
+    __shared__ int s_list[kStageCap];
+    __shared__ int s_list_n;
+    __shared__ int s_ord[kStageCap];
+    __shared__ int s_ord_n;
+    __shared__ int s_fill_n, s_active_n, s_hole_n, s_err_n;
+    __shared__ int s_base;
+    __shared__ int s_frame_fill[kFrameCap];
+    __shared__ int s_frame_k[kFrameCap];
+    __shared__ int s_frame_hole[kFrameCap];
+
+    const int tid = threadIdx.x;
+    const int nblk = (int)gridDim.x;
+    const int lw = logical_block();
+    const int xcd = (int)(blockIdx.x % kXcd);
+    build_offsets(A.eps, s_off, s_rinv, &s_T);
+    if (tid == 0) s_list_n = s_ord_n = s_fill_n = s_active_n = s_hole_n = s_err_n = 0;
+    for (int i = tid; i < kFrameCap; i += kBlock) {
+        s_frame_fill[i] = 0;
+        s_frame_k[i] = 0;
+        s_frame_hole[i] = 0;
+    }
+    __syncthreads();
+    const int T = s_T;
+    int32_t *ctl = A.ctl;
+    const int W = A.W, H = A.H;
+    const bool track = A.tracking != 0;
+
+    // ---- init: copy, shell codes, hole count, shell-0 front ----------------
+    {
+        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+        if (!A.inplace) {
+            const size_t esz = sizeof(TS) * (size_t)A.C;
+            copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
+                       (size_t)lo * esz, (size_t)hi * esz);
+        }
+        Stage st{s_list, &s_list_n};
+        for (long long p = lo + tid; p < hi; p += kBlock) {
+            const uint8_t lab = A.label[p];
+            int32_t code;
+            if (lab == 0) {
+                code = S_READABLE;
+            } else if (lab == 1) {
+                code = S_HOLE;
+                const long long f = p / A.HW;
+                const int q = (int)(p - f * A.HW);
+                if (f < kFrameCap) atomicAdd(&s_frame_hole[f], 1);
+                else atomicAdd(&A.stats[8 + 4 * f + 2], 1);
+                atomicAdd(&s_hole_n, 1);
+                if (track) {
+                    const int y = q / W, x = q - y * W;
+                    const uint8_t *L = A.label + f * A.HW;
+                    bool act = false;
+#pragma unroll
+                    for (int d = 0; d < 9; ++d) {
+                        const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
+                        if (d != 4 && xx >= 0 && xx < W && yy >= 0 && yy < H)
+                            act |= (L[yy * W + xx] == 0);
+                    }
+                    if (act) {
+                        code = S_FRONT;
+                        stage_push(st, (int)p, A.listA, &ctl[G_LIST + 0]);
+                    }
+                }
+            } else {
+                code = S_BYSTANDER;
+                if (lab != 2) atomicAdd(&s_err_n, 1);
+            }
+            A.shell[p] = code;
+        }
+        stage_flush(st, A.listA, &ctl[G_LIST + 0], &s_base);
+        if (tid == 0) {
+            if (s_hole_n) atomicAdd(&ctl[xw(xcd, XF_HOLE)], s_hole_n);
+            if (s_err_n) atomicAdd(&ctl[xw(xcd, XF_ERR)], s_err_n);
+        }
+        for (int i = tid; i < kFrameCap && i < A.B; i += kBlock)
+            if (s_frame_hole[i]) atomicAdd(&A.stats[8 + 4 * i + 2], s_frame_hole[i]);
+    }
+    grid_sync(ctl, (unsigned)nblk);
+
+    // ---- shells -------------------------------------------------------------
+    const int total_hole = sum_x(ctl, XF_HOLE);
+    long long total_filled = 0;
+    int K = 0, max_front = 0, trunc = 0;
+    const int nG = kBlock / G;
+    const int gi = tid / G;       // group within the workgroup
+    const int l = tid & (G - 1);  // lane within the group
+    Stage lst{s_list, &s_list_n};
+    Stage ord{s_ord, &s_ord_n};
+    const bool want_order = A.order != nullptr;
+    int nk = ld_ctl(ctl, G_LIST + 0);
+    for (int k = 0; total_filled < total_hole; ++k) {
+        if (A.max_shells > 0 && k >= A.max_shells) break;
+        if (track && nk == 0) break;
+        if (lw == 0 && tid == 0) {
+            ctl[G_LIST + (k + 2) % 3] = 0;
+            ctl[G_FILL + (k + 1) % 3] = 0;
+            ctl[G_ACTIVE + (k + 1) % 3] = 0;
+        }
+        int32_t *nxt_list = (k & 1) ? A.listA : A.listB;
+        int32_t *nxt_cnt = &ctl[G_LIST + (k + 1) % 3];
+        int my_fill = 0;
+        auto on_filled = [&](long long gidx) {
+            ++my_fill;
+            const long long f = gidx / A.HW;
+            if (want_order) stage_push(ord, (int)gidx, A.order, &ctl[G_ORDER]);
+            if (f < kFrameCap) {
+                atomicAdd(&s_frame_fill[f], 1);
+                atomicMax(&s_frame_k[f], k + 1);
+            } else {
+                int32_t *fs = A.stats + 8 + 4 * f;
+                atomicAdd(&fs[1], 1);
+                atomicMax(&fs[0], k + 1);
+            }
+        };
+        if (track) {
+            const int32_t *cur = (k & 1) ? A.listB : A.listA;
+            const long long lo = (long long)nk * lw / nblk, hi = (long long)nk * (lw + 1) / nblk;
+            for (long long base = lo; base < hi; base += nG) {
+                const long long item = base + gi;
+                if (item < hi) {
+                    const long long gidx = cur[item];
+                    const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, k, l);
+                    const long long f = gidx / A.HW;
+                    const int p = (int)(gidx - f * A.HW);
+                    if (ok) {
+                        if (l < 8) {  // emit the unfilled 8-neighbours (dedup by CAS on the map)
+                            const int d = l < 4 ? l : l + 1;
+                            const int y = p / W, x = p - y * W;
+                            const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
+                            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                                int32_t *sp = A.shell + f * A.HW + (long long)yy * W + xx;
+                                if (*sp == S_HOLE && atomicCAS(sp, S_HOLE, S_FRONT) == S_HOLE)
+                                    stage_push(lst, (int)(f * A.HW + (long long)yy * W + xx),
+                                               nxt_list, nxt_cnt);
+                            }
+                        }
+                        if (l == 0) on_filled(gidx);
+                    } else if (l == 0) {
+                        stage_push(lst, (int)gidx, nxt_list, nxt_cnt);  // not ready: carry over
+                    }
+                }
+            }
+        } else {
+            // one lane per pixel: test membership in the active boundary
+            const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+            const int wave_base = tid & ~63;
+            for (long long base = lo; base < hi; base += kBlock) {
+                const long long p = base + tid;
+                bool act = false;
+                if (p < hi && A.shell[p] == S_HOLE) {
+                    const long long f = p / A.HW;
+                    const int q = (int)(p - f * A.HW);
+                    const int y = q / W, x = q - y * W;
+                    const int32_t *S = A.shell + f * A.HW;
+#pragma unroll
+                    for (int d = 0; d < 9; ++d) {
+                        const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
+                        if (d != 4 && xx >= 0 && xx < W && yy >= 0 && yy < H)
+                            act |= readable(S[yy * W + xx], k);
+                    }
+                }
+                unsigned long long mask = __ballot(act);
+                if (lane_id() == 0 && mask) atomicAdd(&s_active_n, __popcll(mask));
+                const int gpw = 64 / G;         // groups per wavefront
+                const int gw = (tid & 63) / G;  // this lane's group in the wavefront
+                while (mask) {
+                    unsigned long long m2 = mask;
+                    int mybit = -1;
+                    for (int j = 0; j < gpw && m2; ++j) {
+                        const int b = __ffsll((long long)m2) - 1;
+                        m2 &= m2 - 1;
+                        if (j == gw) mybit = b;
+                    }
+                    mask = m2;
+                    if (mybit >= 0) {
+                        const long long px = base + wave_base + mybit;
+                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, k, l);
+                        if (ok && l == 0) on_filled(px);
+                    }
+                }
+            }
+        }
+        if (my_fill) atomicAdd(&s_fill_n, my_fill);
+        if (track) stage_flush(lst, nxt_list, nxt_cnt, &s_base);
+        if (want_order) stage_flush(ord, A.order, &ctl[G_ORDER], &s_base);
+        __syncthreads();
+        if (tid == 0) {
+            if (s_fill_n) atomicAdd(&ctl[G_FILL + k % 3], s_fill_n);
+            if (!track && s_active_n) atomicAdd(&ctl[G_ACTIVE + k % 3], s_active_n);
+            s_fill_n = 0;
+            s_active_n = 0;
+        }
+        grid_sync(ctl, (unsigned)nblk);
+        const int filled_k = ld_ctl(ctl, G_FILL + k % 3);
+        const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + k % 3);
+        if (front_k > max_front) max_front = front_k;
+        if (lw == 0 && tid == 0) {
+            if (A.front_hist && k < A.kcap) A.front_hist[k] = front_k;
+            if (want_order) {
+                if (k + 1 < A.kcap) A.shell_off[k + 1] = ld_ctl(ctl, G_ORDER);
+                else trunc = 1;
+            }
+        }
+        if (filled_k == 0) break;
+        total_filled += filled_k;
+        K = k + 1;
+        nk = ld_ctl(ctl, G_LIST + (k + 1) % 3);
+    }
+
+    // ---- finish -------------------------------------------------------------
+    if (total_filled < total_hole) {  // leftovers never became ready
+        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+        for (long long p = lo + tid; p < hi; p += kBlock) {
+            const int32_t s = A.shell[p];
+            if (s == S_HOLE || s == S_FRONT) A.shell[p] = S_UNFILLED;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < kFrameCap && i < A.B; i += kBlock) {
+        int32_t *fs = A.stats + 8 + 4 * i;
+        if (s_frame_fill[i]) atomicAdd(&fs[1], s_frame_fill[i]);
+        if (s_frame_k[i]) atomicMax(&fs[0], s_frame_k[i]);
+    }
+    if (lw == 0 && tid == 0) {
+        A.stats[0] = K;
+        A.stats[1] = (int32_t)total_filled;
+        A.stats[2] = total_hole;
+        A.stats[3] = max_front;
+        A.stats[4] = sum_x(ctl, XF_ERR);
+        A.stats[5] = trunc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse shells over a recorded fill order
+
+struct BwdArgs {
+    const float *grad_out;
+    const void *img;
+    const float *guide;
+    const int32_t *shell;
+    const int32_t *order;
+    const int32_t *shell_off;
+    float *grad_img;
+    float *grad_guide;
+    int32_t *ctl;
+    long long HW;
+    long long NP;
+    int B, H, W, C, K;
+    int aliased;
+    double eps;
+    double a;
+    int ghost;
+};
+
+template <typename TS, int G>
+__device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rinv, int T,
+                          long long gidx, int k, int l) {
+    const long long f = gidx / A.HW;
+    const int p = (int)(gidx - f * A.HW);
+    const int Y = p / A.W, X = p - Y * A.W;
+    const int W = A.W;
+    const int32_t *S = A.shell + f * A.HW;
+    const float2 gv = reinterpret_cast<const float2 *>(A.guide)[gidx];
+    const double gx = (double)gv.x, gy = (double)gv.y;
+    const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
+    double cs = 0.0, sn = 0.0, L = 1.0;
+    if (rot) {
+        L = sqrt(gx * gx + gy * gy);
+        cs = gx / L;
+        sn = gy / L;
+    }
+    const int C = A.C;
+    const TS *U = reinterpret_cast<const TS *>(A.img) + f * A.HW * C;
+    double q[kPerLaneMax];
+    unsigned rmask = 0;
+    double qmin = INFINITY;
+#pragma unroll
+    for (int r = 0; r < kPerLaneMax; ++r) {
+        q[r] = INFINITY;
+        const int t = l + r * G;
+        if (t < T) {
+            const short2 nm = off[t];
+            double ox, oy;
+            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+            const Support s = support_of(X, Y, ox, oy);
+            bool rd = false;
+            if (s.x0 >= 0 && s.y0 >= 0 && s.x1 < A.W && s.y1 < A.H) {
+                const int32_t a0 = S[s.y0 * W + s.x0], a1 = S[s.y0 * W + s.x1];
+                const int32_t a2 = S[s.y1 * W + s.x0], a3 = S[s.y1 * W + s.x1];
+                rd = ((int)readable(a0, k) & (int)readable(a1, k) & (int)readable(a2, k) &
+                      (int)readable(a3, k)) != 0;
+            }
+            const double tp = (-gy) * ox + gx * oy;
+            q[r] = A.a * tp * tp;
+            if (rd) {
+                rmask |= 1u << r;
+                qmin = fmin(qmin, q[r]);
+            }
+        }
+    }
+    qmin = gmin<G>(qmin);
+    // weights, values and the value of x
+    double w[kPerLaneMax];
+    double v[kPerLaneMax][4];
+    double Ssum = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kPerLaneMax; ++r) {
+        w[r] = 0.0;
+        v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
+        if (rmask & (1u << r)) {
+            const int t = l + r * G;
+            const short2 nm = off[t];
+            double ox, oy;
+            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+            const Support s = support_of(X, Y, ox, oy);
+            w[r] = exp(-(q[r] - qmin)) * rinv[t];
+            Ssum += w[r];
+            const double b00 = s.wx0 * s.wy0, b10 = s.wx1 * s.wy0, b01 = s.wx0 * s.wy1,
+                         b11 = s.wx1 * s.wy1;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ch < C) {
+                    v[r][ch] = b00 * load_px(U + (long long)(s.y0 * W + s.x0) * C + ch) +
+                               b10 * load_px(U + (long long)(s.y0 * W + s.x1) * C + ch) +
+                               b01 * load_px(U + (long long)(s.y1 * W + s.x0) * C + ch) +
+                               b11 * load_px(U + (long long)(s.y1 * W + s.x1) * C + ch);
+                    u[ch] += w[r] * v[r][ch];
+                }
+            }
+        }
+    }
+    Ssum = gsum<G>(Ssum);
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < C) u[ch] = gsum<G>(u[ch]) / Ssum;
+    double ub[4] = {0.0, 0.0, 0.0, 0.0};
+    float *GI = A.grad_img;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < C) ub[ch] = (double)GI[gidx * C + ch];
+    double dgx = 0.0, dgy = 0.0;
+#pragma unroll
+    for (int r = 0; r < kPerLaneMax; ++r) {
+        if (rmask & (1u << r)) {
+            const int t = l + r * G;
+            const short2 nm = off[t];
+            double ox, oy;
+            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+            const Support s = support_of(X, Y, ox, oy);
+            const double lam = w[r] / Ssum;
+            double dox_dgx = 0.0, dox_dgy = 0.0, doy_dgx = 0.0, doy_dgy = 0.0;
+            if (rot) {  // o rotates with g: d(theta) = (c dgy - s dgx) / |g|
+                dox_dgx = sn * oy / L;
+                dox_dgy = -cs * oy / L;
+                doy_dgx = -sn * ox / L;
+                doy_dgy = cs * ox / L;
+            }
+            const double tp = (-gy) * ox + gx * oy;
+            const double dt_dgx = oy + (-gy) * dox_dgx + gx * doy_dgx;
+            const double dt_dgy = -ox + (-gy) * dox_dgy + gx * doy_dgy;
+            const double r2 = ox * ox + oy * oy;
+            const double dlw_dgx = -2.0 * A.a * tp * dt_dgx - (ox * dox_dgx + oy * doy_dgx) / r2;
+            const double dlw_dgy = -2.0 * A.a * tp * dt_dgy - (ox * dox_dgy + oy * doy_dgy) / r2;
+            const bool ex = s.x1 == s.x0, ey = s.y1 == s.y0;
+            const long long i00 = f * A.HW + (long long)s.y0 * W + s.x0;
+            const long long i10 = f * A.HW + (long long)s.y0 * W + s.x1;
+            const long long i01 = f * A.HW + (long long)s.y1 * W + s.x0;
+            const long long i11 = f * A.HW + (long long)s.y1 * W + s.x1;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ch < C) {
+                    const double u00 = load_px(U + (long long)(s.y0 * W + s.x0) * C + ch);
+                    const double u10 = load_px(U + (long long)(s.y0 * W + s.x1) * C + ch);
+                    const double u01 = load_px(U + (long long)(s.y1 * W + s.x0) * C + ch);
+                    const double u11 = load_px(U + (long long)(s.y1 * W + s.x1) * C + ch);
+                    const double vpx = ex ? 0.0 : s.wy0 * (u10 - u00) + s.wy1 * (u11 - u01);
+                    const double vpy = ey ? 0.0 : s.wx0 * (u01 - u00) + s.wx1 * (u11 - u10);
+                    const double dvx = vpx * dox_dgx + vpy * doy_dgx;
+                    const double dvy = vpx * dox_dgy + vpy * doy_dgy;
+                    dgx += ub[ch] * lam * ((v[r][ch] - u[ch]) * dlw_dgx + dvx);
+                    dgy += ub[ch] * lam * ((v[r][ch] - u[ch]) * dlw_dgy + dvy);
+                    // pass the adjoint to the bilinear support
+                    const double g = ub[ch] * lam;
+                    unsafeAtomicAdd(&GI[i00 * C + ch], (float)(g * s.wx0 * s.wy0));
+                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], (float)(g * s.wx1 * s.wy0));
+                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], (float)(g * s.wx0 * s.wy1));
+                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], (float)(g * s.wx1 * s.wy1));
+                }
+            }
+        }
+    }
+    dgx = gsum<G>(dgx);
+    dgy = gsum<G>(dgy);
+    if (l == 0) {
+        A.grad_guide[gidx * 2 + 0] = (float)dgx;
+        A.grad_guide[gidx * 2 + 1] = (float)dgy;
+        for (int ch = 0; ch < C; ++ch) GI[gidx * C + ch] = 0.0f;  // input of a filled pixel is unused
+    }
+}
+
+template <typename TS, int G>
+__global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
+    __shared__ short2 s_off[kMaxOffsets];
+    __shared__ double s_rinv[kMaxOffsets];
+    __shared__ int s_T;
+    const int tid = threadIdx.x;
+    const int nblk = (int)gridDim.x;
+    const int lw = logical_block();
+    build_offsets(A.eps, s_off, s_rinv, &s_T);
+    __syncthreads();
+    const int T = s_T;
+    {
+        // grad_img = grad_out, grad_guide = 0
+        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+        if (!A.aliased)
+            for (long long i = lo * A.C + tid; i < hi * A.C; i += kBlock) A.grad_img[i] = A.grad_out[i];
+        for (long long i = lo * 2 + tid; i < hi * 2; i += kBlock) A.grad_guide[i] = 0.0f;
+    }
+    grid_sync(A.ctl, (unsigned)nblk);
+    const int nG = kBlock / G;
+    const int gi = tid / G, l = tid & (G - 1);
+    for (int k = A.K - 1; k >= 0; --k) {
+        const long long b0 = A.shell_off[k], b1 = A.shell_off[k + 1];
+        const long long n = b1 - b0;
+        const long long lo = b0 + n * lw / nblk, hi = b0 + n * (lw + 1) / nblk;
+        for (long long base = lo; base < hi; base += nG) {
+            const long long item = base + gi;
+            if (item < hi) bwd_pixel<TS, G>(A, s_off, s_rinv, T, (long long)A.order[item], k, l);
+        }
+        grid_sync(A.ctl, (unsigned)nblk);
+    }
+}
+
+}  // namespace gfk

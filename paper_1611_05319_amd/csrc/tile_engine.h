@@ -1,0 +1,512 @@
+// Tiled engine: the shells of Algorithm 1 (Guidefill, arXiv 1611.05319) run
+// S at a time inside LDS-resident tile windows, with one grid barrier per S
+// shells instead of one per shell.
+//
+// A workgroup owns a tile of TW x TH pixels and stages a window that extends
+// Hh = S * ceil(eps) pixels beyond it (states and colours in LDS).  Every
+// dependency of a pixel in one shell lies within ceil(eps) pixels (the bilinear
+// support of the ball and the 8-neighbourhood), so after j local shells the
+// window is exact at distance >= j * ceil(eps) from its edge: the tile interior
+// is exact through S shells.  Only interior results are written back; pixels
+// filled in the current pass by neighbouring tiles are recomputed locally, so
+// no workgroup waits for another inside a pass.
+//
+// Tracking (Sec. 3.5) works at two levels: inside a window a local front list
+// gives lanes only to the active boundary (CAS dedup on the LDS state, carry
+// over of waiting pixels); across the frame only tiles whose 3 x 3 tile
+// neighbourhood filled something in the previous pass are visited (the halo
+// never reaches beyond the neighbouring tiles, Hh <= min(TW, TH), and a window
+// whose content did not change fills nothing again).  The untracked form
+// visits every tile in every pass and gives every window pixel a lane in every
+// shell.
+#pragma once
+
+#include "global_engine.h"
+
+namespace gfk {
+
+struct TileArgs {
+    const void *in;
+    void *out;
+    const uint8_t *label;
+    const float *guide;
+    int32_t *shell;
+    int32_t *stats;
+    int32_t *front_hist;
+    int32_t *ctl;
+    int32_t *t_hole, *t_rem, *t_kmax, *t_fill, *t_mark;
+    int32_t *act0, *act1;  // 8 segments of ntiles entries each
+    long long HW, NP;
+    int B, H, W, C, kcap;
+    int TW, TH, S, Hh, WW, WH, WN;
+    int tiles_x, tiles_y, ntiles;
+    int max_shells, inplace, ghost, tile_track, local_track;
+    double eps, a, c;
+};
+
+// Optional timing hooks (compiled in only with -DGF_TRACE, for profiling
+// builds): per-workgroup accumulators of wall-clock ticks and counts.
+#ifdef GF_TRACE
+constexpr int kTraceSlots = 16;
+__device__ long long gf_trace[4096 * kTraceSlots];
+#define GF_T0() long long gf_t_last = wall_clock64()
+#define GF_TACC(slot)                                                                   \
+    do {                                                                                \
+        if (threadIdx.x == 0) {                                                         \
+            const long long gf_t_now = wall_clock64();                                  \
+            gf_trace[blockIdx.x * kTraceSlots + (slot)] += gf_t_now - gf_t_last;        \
+            gf_t_last = gf_t_now;                                                       \
+        }                                                                               \
+    } while (0)
+#define GF_TCNT(slot, v)                                                                \
+    do {                                                                                \
+        if (threadIdx.x == 0) gf_trace[blockIdx.x * kTraceSlots + (slot)] += (v);       \
+    } while (0)
+#else
+#define GF_T0()
+#define GF_TACC(slot)
+#define GF_TCNT(slot, v)
+#endif
+
+constexpr int kTileBlock = 1024;  // one 16-wave workgroup per CU
+constexpr int kWinPerThread = 8;  // window pixels staged per thread per round trip
+constexpr int kMaxWindow = kTileBlock * kWinPerThread;
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// LDS of one window: states (int32), colours (storage type), guide (float2),
+// two local front lists (uint16)
+template <typename TS> __host__ __device__ inline size_t tile_lds_bytes(int WN, int C) {
+    return align16((size_t)WN * 4) + align16((size_t)WN * C * sizeof(TS)) +
+           align16((size_t)WN * 8) + (size_t)WN * 4;
+}
+
+template <typename TS, int G>
+__global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ short2 s_off[kMaxOffsets];
+    __shared__ double s_rinv[kMaxOffsets];
+    __shared__ int s_T;
+    __shared__ int s_stage[kStageCap];
+    __shared__ int s_stage_n;
+    __shared__ int s_base;
+    __shared__ int s_fn[2];       // local front lengths
+    __shared__ int s_filled_j;    // pixels filled in the window in the current local shell
+    __shared__ int s_r[4];        // tile reductions: filled, remaining, kmax
+    __shared__ int s_pass_fill, s_pass_kmax, s_hole_n, s_err_n;
+    __shared__ int s_front_in[32];  // interior active pixels per local shell
+    __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
+
+    const int tid = threadIdx.x;
+    const int nblk = (int)gridDim.x;
+    const int lw = logical_block();
+    const int xcd = (int)(blockIdx.x % kXcd);
+    const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
+    int32_t *st = reinterpret_cast<int32_t *>(smem);
+    TS *col = reinterpret_cast<TS *>(smem + align16((size_t)WN * 4));
+    float2 *gd = reinterpret_cast<float2 *>(smem + align16((size_t)WN * 4) +
+                                            align16((size_t)WN * C * sizeof(TS)));
+    uint16_t *fl = reinterpret_cast<uint16_t *>(smem + align16((size_t)WN * 4) +
+                                                align16((size_t)WN * C * sizeof(TS)) +
+                                                align16((size_t)WN * 8));
+    int32_t *ctl = A.ctl;
+    build_offsets(A.eps, s_off, s_rinv, &s_T);
+    if (tid == 0) {
+        s_stage_n = 0;
+        s_hole_n = 0;
+        s_err_n = 0;
+        s_r[0] = s_r[1] = s_r[2] = s_r[3] = 0;
+    }
+    __syncthreads();
+    const int T = s_T;
+    const int tpf = A.tiles_x * A.tiles_y;  // tiles per frame
+    Stage stage{s_stage, &s_stage_n};
+    GF_T0();
+
+    // ---- phase A: copy, shell codes, per-tile hole counts, pass-0 tiles ----
+    if (!A.inplace) {
+        const size_t esz = sizeof(TS) * (size_t)C;
+        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+        copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
+                   (size_t)lo * esz, (size_t)hi * esz);
+    }
+    {
+        const int tpx = A.TW * A.TH;
+        int nb = (kWinPerThread * kTileBlock) / tpx;  // tiles per batch: <= 8 labels per thread
+        nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
+        for (int b0 = 0; lw + b0 * nblk < A.ntiles; b0 += nb) {
+            if (tid < 16) s_tcnt[tid] = 0;
+            __syncthreads();
+            for (int sb = 0; sb < nb * tpx; sb += kWinPerThread * kTileBlock) {
+            uint8_t lab[kWinPerThread];
+            long long pix[kWinPerThread];
+            int tj[kWinPerThread];
+#pragma unroll
+            for (int r = 0; r < kWinPerThread; ++r) {
+                const int slot = sb + tid + r * kTileBlock;
+                tj[r] = -1;
+                pix[r] = 0;
+                lab[r] = 0;
+                const int j = slot / tpx, i = slot - j * tpx;
+                const int t = lw + (b0 + j) * nblk;
+                if (j < nb && t < A.ntiles) {
+                    const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
+                    const int y = ty * A.TH + i / A.TW, x = tx * A.TW + i % A.TW;
+                    if (x < W && y < H) {
+                        tj[r] = j;
+                        pix[r] = (long long)f * A.HW + (long long)y * W + x;
+                        lab[r] = A.label[pix[r]];
+                    }
+                }
+            }
+            int ne = 0;
+#pragma unroll
+            for (int r = 0; r < kWinPerThread; ++r) {
+                if (tj[r] < 0) continue;
+                int32_t code = S_BYSTANDER;
+                if (lab[r] == 0) code = S_READABLE;
+                else if (lab[r] == 1) { code = S_HOLE; atomicAdd(&s_tcnt[tj[r]], 1); }
+                else if (lab[r] != 2) ++ne;
+                A.shell[pix[r]] = code;
+            }
+            if (ne) atomicAdd(&s_err_n, ne);
+            }
+            __syncthreads();
+            if (tid < nb) {
+                const int t = lw + (b0 + tid) * nblk;
+                if (t < A.ntiles) {
+                    const int h = s_tcnt[tid];
+                    A.t_hole[t] = h;
+                    A.t_rem[t] = h;
+                    A.t_fill[t] = 0;
+                    A.t_kmax[t] = 0;
+                    A.t_mark[t] = 0;
+                    if (h && A.tile_track)
+                        stage_push(stage, t, A.act0 + (long long)xcd * A.ntiles,
+                                   &ctl[xw(xcd, XF_ACT + 0)]);
+                    if (h) atomicAdd(&s_hole_n, h);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    stage_flush(stage, A.act0 + (long long)xcd * A.ntiles, &ctl[xw(xcd, XF_ACT + 0)], &s_base);
+    if (tid == 0) {
+        if (s_hole_n) atomicAdd(&ctl[xw(xcd, XF_HOLE)], s_hole_n);
+        if (s_err_n) atomicAdd(&ctl[xw(xcd, XF_ERR)], s_err_n);
+    }
+    GF_TACC(0);
+    grid_sync(ctl, (unsigned)nblk);
+    GF_TACC(5);
+
+    // ---- passes of S shells -------------------------------------------------
+    const int total_hole = sum_x(ctl, XF_HOLE);
+    long long total_filled = 0;
+    const int nG = kTileBlock / G;
+    const int gi = tid / G, l = tid & (G - 1);
+    const int wave_base = tid & ~63;
+    for (int p = 0; total_filled < total_hole; ++p) {
+        const int k0 = p * A.S;
+        if (A.max_shells > 0 && k0 >= A.max_shells) break;
+        const int Sp = A.max_shells > 0 ? min(A.S, A.max_shells - k0) : A.S;
+        if (lw == 0 && tid < kXcd) {
+            ctl[xw(tid, XF_ACT + (p + 2) % 3)] = 0;
+            ctl[xw(tid, XF_PFILL + (p + 1) % 3)] = 0;
+        }
+        if (tid == 0) {
+            s_pass_fill = 0;
+            s_pass_kmax = 0;
+        }
+        int32_t *cur_act = (p & 1) ? A.act1 : A.act0;
+        int32_t *nxt_act = ((p & 1) ? A.act0 : A.act1) + (long long)xcd * A.ntiles;
+        int32_t *nxt_cnt = &ctl[xw(xcd, XF_ACT + (p + 1) % 3)];
+        int seg[kXcd];
+        int n_tiles_pass = 0;
+        if (A.tile_track) {
+#pragma unroll
+            for (int x = 0; x < kXcd; ++x) {
+                seg[x] = ld_ctl(ctl, xw(x, XF_ACT + p % 3));
+                n_tiles_pass += seg[x];
+            }
+        } else {
+            n_tiles_pass = A.ntiles;
+        }
+        __syncthreads();
+        for (int v = lw; v < n_tiles_pass; v += nblk) {
+            int t = v;
+            if (A.tile_track) {
+                int i = v, x = 0;
+#pragma unroll
+                for (int xx = 0; xx < kXcd - 1; ++xx)
+                    if (x == xx && i >= seg[xx]) { i -= seg[xx]; x = xx + 1; }
+                t = cur_act[(long long)x * A.ntiles + i];
+                if (A.t_rem[t] == 0) continue;  // uniform across the workgroup
+            }
+            const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
+            const int ox0 = tx * A.TW - A.Hh, oy0 = ty * A.TH - A.Hh;
+            const int32_t *S = A.shell + (long long)f * A.HW;
+            const TS *U = reinterpret_cast<const TS *>(A.out) + (long long)f * A.HW * C;
+            const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
+            // 1. stage the window in two round trips: states (readable before the
+            //    pass / bystander / hole; pixels filled by neighbours during this pass
+            //    count as hole), then colours of readable and guides of hole pixels
+            for (int base = 0; base < WN; base += kWinPerThread * kTileBlock) {
+                int32_t code[kWinPerThread];
+#pragma unroll
+                for (int r = 0; r < kWinPerThread; ++r) {
+                    const int i = base + tid + r * kTileBlock;
+                    code[r] = S_BYSTANDER;
+                    if (i < WN) {
+                        const int wy = i / WW, wx = i - wy * WW;
+                        const int x = ox0 + wx, y = oy0 + wy;
+                        if (x >= 0 && x < W && y >= 0 && y < H) {
+                            const int32_t s = S[y * W + x];
+                            code[r] = (s == -1 || (s >= 0 && s < k0)) ? S_READABLE
+                                      : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kWinPerThread; ++r) {
+                    const int i = base + tid + r * kTileBlock;
+                    if (i < WN) {
+                        st[i] = code[r];
+                        const int wy = i / WW, wx = i - wy * WW;
+                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
+                        if (code[r] == S_READABLE) {
+                            for (int ch = 0; ch < C; ++ch) col[i * C + ch] = U[q * C + ch];
+                        } else if (code[r] == S_HOLE) {
+                            gd[i] = Gd[q];
+                        }
+                    }
+                }
+            }
+            if (tid == 0) {
+                s_fn[0] = s_fn[1] = 0;
+                s_filled_j = 0;
+            }
+            if (tid < 32) s_front_in[tid] = 0;
+            __syncthreads();
+            GF_TACC(1);
+            GF_TCNT(6, 1);
+            // 2. local shells
+            if (A.local_track) {
+                for (int i = tid; i < WN; i += kTileBlock) {
+                    if (st[i] != S_HOLE) continue;
+                    const int wy = i / WW, wx = i - wy * WW;
+                    bool act = false;
+#pragma unroll
+                    for (int d = 0; d < 9; ++d) {
+                        const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
+                        if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
+                            act |= (st[yy * WW + xx] == S_READABLE);
+                    }
+                    if (act) {
+                        st[i] = S_FRONT;
+                        fl[atomicAdd(&s_fn[0], 1)] = (uint16_t)i;
+                    }
+                }
+                __syncthreads();
+            }
+            GF_TACC(2);
+            LdsView<TS> view{st, col, WW, A.WH, C};
+            int cur = 0;
+            for (int j = 0; j < Sp; ++j) {
+                auto fill_one = [&](int wi) -> bool {
+                    const int Y = wi / WW, X = wi - Y * WW;
+                    const float2 gv = gd[wi];
+                    double val[4];
+                    const bool ok = fill_core<TS, G>(view, X, Y, (double)gv.x, (double)gv.y,
+                                                     A.ghost != 0, s_off, s_rinv, T, j, l, A.a,
+                                                     A.c, val);
+                    if (l == 0) {
+                        if (X >= A.Hh && X < A.Hh + A.TW && Y >= A.Hh && Y < A.Hh + A.TH)
+                            atomicAdd(&s_front_in[j & 31], 1);
+                        if (ok) {
+                            for (int ch = 0; ch < C; ++ch) col[wi * C + ch] = to_storage<TS>(val[ch]);
+                            st[wi] = j;
+                            atomicAdd(&s_filled_j, 1);
+                        }
+                    }
+                    return ok;
+                };
+                if (A.local_track) {
+                    const int n = s_fn[cur];
+                    GF_TCNT(7, n);
+                    GF_TCNT(8, 1);
+                    const uint16_t *list = fl + cur * WN;
+                    uint16_t *nlist = fl + (cur ^ 1) * WN;
+                    for (int base = 0; base < n; base += nG) {
+                        const int item = base + gi;
+                        if (item < n) {
+                            const int wi = list[item];
+                            const bool ok = fill_one(wi);
+                            if (ok) {
+                                if (l < 8) {  // emit unfilled 8-neighbours, CAS dedup
+                                    const int d = l < 4 ? l : l + 1;
+                                    const int Y = wi / WW, X = wi - Y * WW;
+                                    const int xx = X + d % 3 - 1, yy = Y + d / 3 - 1;
+                                    if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH) {
+                                        const int nw = yy * WW + xx;
+                                        if (st[nw] == S_HOLE && atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
+                                            nlist[atomicAdd(&s_fn[cur ^ 1], 1)] = (uint16_t)nw;
+                                    }
+                                }
+                            } else if (l == 0) {
+                                nlist[atomicAdd(&s_fn[cur ^ 1], 1)] = (uint16_t)wi;  // carry over
+                            }
+                        }
+                    }
+                } else {
+                    for (int base = 0; base < WN; base += kTileBlock) {
+                        const int i = base + tid;
+                        bool act = false;
+                        if (i < WN && st[i] == S_HOLE) {
+                            const int wy = i / WW, wx = i - wy * WW;
+#pragma unroll
+                            for (int d = 0; d < 9; ++d) {
+                                const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
+                                if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
+                                    act |= readable(st[yy * WW + xx], j);
+                            }
+                        }
+                        unsigned long long mask = __ballot(act);
+                        const int gpw = 64 / G, gw = (tid & 63) / G;
+                        while (mask) {
+                            unsigned long long m2 = mask;
+                            int mybit = -1;
+                            for (int q = 0; q < gpw && m2; ++q) {
+                                const int b = __ffsll((long long)m2) - 1;
+                                m2 &= m2 - 1;
+                                if (q == gw) mybit = b;
+                            }
+                            mask = m2;
+                            if (mybit >= 0) fill_one(base + wave_base + mybit);
+                        }
+                    }
+                }
+                __syncthreads();
+                const int filled = s_filled_j;
+                __syncthreads();
+                if (tid == 0) {
+                    s_filled_j = 0;
+                    s_fn[cur] = 0;
+                }
+                cur ^= 1;
+                __syncthreads();
+                if (filled == 0) break;  // the window can no longer change in this pass
+            }
+            GF_TACC(3);
+            // 3. write back the interior; tile bookkeeping
+            {
+                int nf = 0, nr = 0, km = 0;
+                const int tw = min(A.TW, W - tx * A.TW), th = min(A.TH, H - ty * A.TH);
+                TS *O = reinterpret_cast<TS *>(A.out) + (long long)f * A.HW * C;
+                int32_t *Sw = A.shell + (long long)f * A.HW;
+                for (int i = tid; i < tw * th; i += kTileBlock) {
+                    const int ly = i / tw, lx = i - ly * tw;
+                    const int wi = (ly + A.Hh) * WW + (lx + A.Hh);
+                    const int v = st[wi];
+                    const int y = ty * A.TH + ly, x = tx * A.TW + lx;
+                    if (v >= 0) {
+                        Sw[y * W + x] = k0 + v;
+                        for (int ch = 0; ch < C; ++ch) O[(long long)(y * W + x) * C + ch] = col[wi * C + ch];
+                        ++nf;
+                        km = max(km, k0 + v + 1);
+                    } else if (v == S_HOLE || v == S_FRONT) {
+                        ++nr;
+                    }
+                }
+                if (nf) atomicAdd(&s_r[0], nf);
+                if (nr) atomicAdd(&s_r[1], nr);
+                if (km) atomicMax(&s_r[2], km);
+                __syncthreads();
+                const int tf = s_r[0];
+                if (tid == 0) {
+                    A.t_rem[t] = s_r[1];
+                    if (tf) {
+                        A.t_fill[t] += tf;
+                        A.t_kmax[t] = max(A.t_kmax[t], s_r[2]);
+                        s_pass_fill += tf;
+                        s_pass_kmax = max(s_pass_kmax, s_r[2]);
+                    }
+                    if (A.front_hist)
+                        for (int j = 0; j < Sp && j < 32; ++j)
+                            if (s_front_in[j] && k0 + j < A.kcap) atomicAdd(&A.front_hist[k0 + j], s_front_in[j]);
+                }
+                if (tf && A.tile_track && tid < 9) {  // the 3 x 3 tile neighbourhood may change next pass
+                    const int nx = tx + tid % 3 - 1, ny = ty + tid / 3 - 1;
+                    if (nx >= 0 && nx < A.tiles_x && ny >= 0 && ny < A.tiles_y) {
+                        const int n = f * tpf + ny * A.tiles_x + nx;
+                        if (A.t_hole[n] > 0 && atomicMax(&A.t_mark[n], p + 1) < p + 1)
+                            stage_push(stage, n, nxt_act, nxt_cnt);
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) s_r[0] = s_r[1] = s_r[2] = 0;
+                __syncthreads();
+            }
+            GF_TACC(4);
+        }
+        stage_flush(stage, nxt_act, nxt_cnt, &s_base);
+        if (tid == 0 && s_pass_fill) {
+            atomicAdd(&ctl[xw(xcd, XF_PFILL + p % 3)], s_pass_fill);
+            atomicMax(&ctl[xw(xcd, XF_KMAX)], s_pass_kmax);
+        }
+        GF_TACC(9);
+        grid_sync(ctl, (unsigned)nblk);
+        GF_TACC(5);
+        GF_TCNT(10, 1);
+        const int fills = sum_x(ctl, XF_PFILL + p % 3);
+        if (fills == 0) break;
+        total_filled += fills;
+    }
+
+    // ---- finish ---------------------------------------------------------------
+    if (total_filled < total_hole) {  // leftovers never became ready: shell -3
+        for (int t = lw; t < A.ntiles; t += nblk) {
+            if (A.t_rem[t] == 0) continue;
+            const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
+            const int tw = min(A.TW, W - tx * A.TW), th = min(A.TH, H - ty * A.TH);
+            int32_t *Sw = A.shell + (long long)f * A.HW;
+            for (int i = tid; i < tw * th; i += kTileBlock) {
+                const int y = ty * A.TH + i / tw, x = tx * A.TW + i % tw;
+                if (Sw[y * W + x] == S_HOLE) Sw[y * W + x] = S_UNFILLED;
+            }
+        }
+    }
+    for (int f = lw; f < A.B; f += nblk) {  // per-frame statistics, one workgroup per frame
+        int kf = 0, ff = 0, hf = 0;
+        for (int i = tid; i < tpf; i += kTileBlock) {
+            const int t = f * tpf + i;
+            kf = max(kf, A.t_kmax[t]);
+            ff += A.t_fill[t];
+            hf += A.t_hole[t];
+        }
+        if (kf) atomicMax(&s_r[2], kf);
+        if (ff) atomicAdd(&s_r[0], ff);
+        if (hf) atomicAdd(&s_r[1], hf);
+        __syncthreads();
+        if (tid == 0) {
+            A.stats[8 + 4 * f + 0] = s_r[2];
+            A.stats[8 + 4 * f + 1] = s_r[0];
+            A.stats[8 + 4 * f + 2] = s_r[1];
+            s_r[0] = s_r[1] = s_r[2] = 0;
+        }
+        __syncthreads();
+    }
+    if (lw == 0 && tid == 0) {
+        const int K = max_x(ctl, XF_KMAX);
+        int mf = 0;
+        if (A.front_hist)
+            for (int k = 0; k < K && k < A.kcap; ++k) mf = max(mf, A.front_hist[k]);
+        A.stats[0] = K;
+        A.stats[1] = (int32_t)total_filled;
+        A.stats[2] = total_hole;
+        A.stats[3] = mf;
+        A.stats[4] = sum_x(ctl, XF_ERR);
+        A.stats[5] = 0;
+    }
+}
+
+}  // namespace gfk

@@ -53,11 +53,15 @@ def test_version_and_status_strings(lib):
 def test_workspace_size(lib):
     import paper_1611_05319_amd as gf
 
-    p = gf.Params().c_struct()
+    p = gf.Params(engine=gf.ENGINE_FRONT).c_struct()
     n1 = lib.gf_workspace_size(1, 1080, 1920, 3, 0, ctypes.byref(p))
     n2 = lib.gf_workspace_size(2, 1080, 1920, 3, 0, ctypes.byref(p))
     assert n1 >= 2 * 1080 * 1920 * 4 and n2 > n1
     assert n1 % 256 == 0
+    t = gf.Params().c_struct()  # tiled engine: per-tile words only
+    m1 = lib.gf_workspace_size(1, 1080, 1920, 3, 0, ctypes.byref(t))
+    m2 = lib.gf_workspace_size(4, 1080, 1920, 3, 0, ctypes.byref(t))
+    assert 0 < m1 < n1 and m2 > m1
     assert lib.gf_workspace_size(0, 10, 10, 3, 0, ctypes.byref(p)) == 0
     assert lib.gf_backward_workspace_size(1, 10, 10, 3, 0, ctypes.byref(p)) >= 256
 
@@ -73,7 +77,8 @@ def _call(lib, params, B=1, H=8, W=8, C=3, dt=0, ptr=1 << 20, ws_bytes=1 << 20, 
 @pytest.mark.parametrize("field,value", [
     ("eps", 0.0), ("eps", 0.5), ("eps", 9.5), ("eps", float("nan")), ("mu", 0.0),
     ("mu", -1.0), ("mu", float("inf")), ("c", float("nan")), ("max_shells", -1),
-    ("group", 16), ("blocks_per_cu", 9), ("blocks_per_cu", -1)])
+    ("group", 4), ("blocks_per_cu", 9), ("blocks_per_cu", -1), ("engine", 2), ("engine", -1),
+    ("pass_shells", 33), ("pass_shells", -1), ("tile_w", 300), ("tile_h", -2)])
 def test_bad_parameters_are_rejected(lib, field, value):
     import paper_1611_05319_amd as gf
 
@@ -89,6 +94,33 @@ def test_bad_shapes_are_rejected(lib, shape):
 
     B, H, W, C = shape
     assert _call(lib, gf.Params().c_struct(), B=B, H=H, W=W, C=C) == -1
+
+
+def test_tile_halo_must_fit_the_neighbour_tiles(lib):
+    import paper_1611_05319_amd as gf
+
+    # halo pass_shells * ceil(eps) = 12 > tile 8: the tile tracking would be inexact
+    p = gf.Params(tile_w=8, tile_h=8, pass_shells=4).c_struct()
+    assert _call(lib, p) == -1
+    out = (ctypes.c_int32 * 6)()
+    assert lib.gf_tile_geometry(64, 64, 3, 0, ctypes.byref(p), out) == -1
+    q = gf.Params().c_struct()
+    assert lib.gf_tile_geometry(1080, 1920, 3, 0, ctypes.byref(q), out) == 0
+    tw, th, S, halo, lds, G = list(out)
+    assert halo == S * 3 and halo <= tw and halo <= th and G in (8, 16, 32, 64)
+    f = gf.Params(engine=gf.ENGINE_FRONT, group=8).c_struct()  # 8 lanes: tiled engine only
+    assert _call(lib, f) == -1
+    q5 = gf.Params(eps=5.0, mu=100.0).c_struct()
+    assert lib.gf_tile_geometry(2160, 3840, 3, 0, ctypes.byref(q5), out) == 0
+    assert out[3] == out[2] * 5 and out[3] <= out[0]
+
+
+def test_order_needs_the_front_engine(lib):
+    import paper_1611_05319_amd as gf
+
+    p = gf.Params(engine=gf.ENGINE_TILED).c_struct()
+    assert _call(lib, p, order=ctypes.c_void_p(1 << 20), offs=ctypes.c_void_p(1 << 21),
+                 kcap=4) == -3
 
 
 def test_bad_pointers_and_workspace_are_rejected(lib):

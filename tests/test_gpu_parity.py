@@ -27,8 +27,12 @@ def _device():
     gf.load()
 
 
-def _check(img, lab, g, eps=3.0, mu=50.0, c=-1.0, ghost=True, tracking=True, **kw):
-    ref = oracle.fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost)
+ENGINES = [0, 1]  # tiled, global front
+
+
+def _check(img, lab, g, eps=3.0, mu=50.0, c=-1.0, ghost=True, tracking=True, ref=None, **kw):
+    if ref is None:
+        ref = oracle.fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost)
     u, s, st, _ = gpu_fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking, **kw)
     np.testing.assert_array_equal(s, ref.shell)
     worst = assert_colour_parity(u, ref.u, ref.shell)
@@ -41,10 +45,12 @@ def _check(img, lab, g, eps=3.0, mu=50.0, c=-1.0, ghost=True, tracking=True, **k
 
 def test_config1_tracked_and_untracked():
     w = syn.config1()
-    for tracking in (True, False):
-        for ghost in (True, False):
-            banner(f"c1 tracking={tracking} ghost={ghost}")
-            _check(w.image[0], w.label[0], w.guide[0], ghost=ghost, tracking=tracking)
+    for engine in ENGINES:
+        for tracking in (True, False):
+            for ghost in (True, False):
+                banner(f"c1 engine={engine} tracking={tracking} ghost={ghost}")
+                _check(w.image[0], w.label[0], w.guide[0], ghost=ghost, tracking=tracking,
+                       engine=engine)
 
 
 CASES = [
@@ -65,17 +71,19 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}-e{c[3]}-c{c[5]}-g{int(c[6])}" for c in CASES])
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("tracking", [True, False])
-def test_random_problems(case, tracking):
+def test_random_problems(case, tracking, engine):
     H, W, C, eps, mu, c, ghost, ph, pb = case
-    banner(f"random {case} tracking={tracking}")
+    banner(f"random {case} tracking={tracking} engine={engine}")
     rng = np.random.default_rng(hash(case) % (1 << 32))
     img, lab, g = syn.random_tiny(rng, H, W, C=C, p_hole=ph, p_bystander=pb,
                                   blob=min(H, W) > 4)
     ref = oracle.fill(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost)
     if c >= 0:
         assert ref.n_ties == 0, "confidence within the tie band of the threshold"
-    _check(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking)
+    _check(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking, ref=ref,
+           engine=engine)
 
 
 def test_lattice_line_angles():
@@ -87,12 +95,15 @@ def test_lattice_line_angles():
     pick = rng.integers(0, len(angles), size=(H, W))
     g = np.stack([np.cos(angles[pick]), np.sin(angles[pick])], -1).astype(np.float32)
     g = np.where((lab == 1)[..., None], g, np.float32(0))
-    for tracking in (True, False):
-        banner(f"lattice-line angles tracking={tracking}")
-        _check(img, lab, g, tracking=tracking)
+    ref = oracle.fill(img, lab, g)
+    for engine in ENGINES:
+        for tracking in (True, False):
+            banner(f"lattice-line angles tracking={tracking} engine={engine}")
+            _check(img, lab, g, tracking=tracking, engine=engine, ref=ref)
 
 
-def test_edge_cases():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_edge_cases(engine):
     rng = np.random.default_rng(8)
     img = rng.uniform(0, 1, size=(40, 50, 3)).astype(np.float32)
     g = np.zeros((40, 50, 2), np.float32)
@@ -100,12 +111,12 @@ def test_edge_cases():
     # no hole at all
     banner("edge: no hole")
     lab = np.zeros((40, 50), np.uint8)
-    ref, u, s, st, _ = _check(img, lab, g)
+    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
     assert st["K"] == 0 and st["hole"] == 0
     # everything is hole: nothing readable, nothing filled
     banner("edge: all hole")
     lab = np.ones((40, 50), np.uint8)
-    ref, u, s, st, _ = _check(img, lab, g)
+    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
     assert (s == -3).all() and st["filled"] == 0
     # hole surrounded by bystanders (stall), and a hole on the image border
     banner("edge: stall")
@@ -113,7 +124,7 @@ def test_edge_cases():
     lab[10:30, 10:30] = 2
     lab[15:25, 15:25] = 1
     lab[0:3, 40:50] = 1
-    ref, u, s, st, _ = _check(img, lab, g)
+    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
     assert (s[15:25, 15:25] == -3).all() and st["unfilled"] == 100
     # label values outside {0, 1, 2} are counted and act as bystanders
     banner("edge: bad labels")
@@ -123,7 +134,7 @@ def test_edge_cases():
     ref_lab = lab.copy()
     ref_lab[20, 20] = 2
     ref = oracle.fill(img, ref_lab, g)
-    u, s, st, _ = gpu_fill(img, lab, g)
+    u, s, st, _ = gpu_fill(img, lab, g, engine=engine)
     np.testing.assert_array_equal(s, ref.shell)
     assert st["label_errors"] == 1
 
@@ -140,33 +151,58 @@ def test_constant_image_is_exact():
                                                             u[filled].shape))
 
 
+FORMS = [
+    {"engine": 1}, {"engine": 1, "tracking": False}, {"tracking": False}, {"inplace": True},
+    {"engine": 1, "inplace": True}, {"group": 8}, {"group": 16}, {"group": 32}, {"group": 64},
+    {"engine": 1, "group": 16}, {"blocks_per_cu": 1}, {"blocks_per_cu": 4},
+    {"tile_w": 12, "tile_h": 12, "pass_shells": 1}, {"tile_w": 16, "tile_h": 24, "pass_shells": 2},
+    {"tile_w": 40, "tile_h": 40, "pass_shells": 8}, {"tile_w": 24, "tile_h": 24, "pass_shells": 6},
+    {"tile_w": 64, "tile_h": 16, "pass_shells": 5}, {"tile_w": 20, "tile_h": 36, "pass_shells": 3},
+    {"tile_w": 24, "tile_h": 24, "pass_shells": 8, "tracking": False},
+    {"tile_w": 100, "tile_h": 120, "pass_shells": 2}, {},
+]
+
+
 def test_forms_agree_exactly():
-    banner("forms: tracked/untracked, in place, groups, batched, repeat")
+    banner("forms: engines, tracking, in place, groups, tiles, repeat")
     w = syn.config1(seed=11, H=200, W=240)
     img, lab, g = w.image[0], w.label[0], w.guide[0]
+    ref = oracle.fill(img, lab, g)
     u0, s0, st0, _ = gpu_fill(img, lab, g)
-    for kw in ({"tracking": False}, {"inplace": True}, {"group": 64}, {"blocks_per_cu": 1},
-               {"blocks_per_cu": 8}, {}):
+    np.testing.assert_array_equal(s0, ref.shell)
+    import paper_1611_05319_amd as gf
+
+    for kw in FORMS:
+        if "tile_w" in kw:
+            try:  # windows larger than the device's LDS per workgroup are rejected
+                gf.tile_geometry(200, 240, 3, params=gf.Params(**{k: v for k, v in kw.items()
+                                                                  if k != "inplace"}))
+            except RuntimeError:
+                banner(f"form {kw}: window does not fit, skipped")
+                continue
+        banner(f"form {kw}")
         u1, s1, st1, _ = gpu_fill(img, lab, g, **kw)
         np.testing.assert_array_equal(s1, s0)
-        if "group" in kw:   # another reduction tree: FP64 sums differ in the last bits
+        G = kw.get("group") or (32 if kw.get("engine") == 1 else 8)
+        if G != 8:  # another reduction tree: the last FP64 bits may differ
             assert np.abs(u1 - u0).max() <= 2.0 ** -23
         else:
             np.testing.assert_array_equal(u1, u0)
-        assert st1["K"] == st0["K"]
+        assert st1["K"] == st0["K"] and st1["filled"] == st0["filled"]
     # batched frames give the per-frame results
     rng = np.random.default_rng(12)
     frames = [syn.random_tiny(rng, 64, 80, C=3, p_hole=p, p_bystander=0.05) for p in (0.1, 0.3, 0.6)]
     bi = np.stack([f[0] for f in frames])
     bl = np.stack([f[1] for f in frames])
     bg = np.stack([f[2] for f in frames])
-    ub, sb, stb, _ = gpu_fill(bi, bl, bg)
-    for i, (fi, fl, fg) in enumerate(frames):
-        ui, si, sti, _ = gpu_fill(fi, fl, fg)
-        np.testing.assert_array_equal(sb[i], si)
-        np.testing.assert_array_equal(ub[i], ui)
-        assert stb["frame_K"][i] == sti["K"] and stb["frame_filled"][i] == sti["filled"]
-        assert stb["frame_hole"][i] == sti["hole"]
+    for engine in ENGINES:
+        ub, sb, stb, _ = gpu_fill(bi, bl, bg, engine=engine)
+        for i, (fi, fl, fg) in enumerate(frames):
+            ui, si, sti, _ = gpu_fill(fi, fl, fg, engine=engine)
+            np.testing.assert_array_equal(sb[i], si)
+            np.testing.assert_array_equal(ub[i], ui)
+            assert stb["frame_K"][i] == sti["K"] and stb["frame_filled"][i] == sti["filled"]
+            assert stb["frame_hole"][i] == sti["hole"]
 
 
 def test_front_sizes_match_active_boundary():
@@ -174,34 +210,41 @@ def test_front_sizes_match_active_boundary():
     banner("front sizes")
     rng = np.random.default_rng(6)
     img, lab, g = syn.random_tiny(rng, 120, 150, C=3, p_hole=0.5, p_bystander=0.08)
-    ref = oracle.fill(img, lab, g)
-    for tracking in (True, False):
-        u, s, st, r = gpu_fill(img, lab, g, tracking=tracking, record_fronts=True)
-        hist = r.front_hist.cpu().numpy()
+    for ghost in (True, False):
+        ref = oracle.fill(img, lab, g, ghost=ghost)
         K = ref.K
-        np.testing.assert_array_equal(hist[:K], ref.front_hist[0, :K])
-        assert st["max_front"] == ref.max_front
+        for tracking in (True, False):
+            # the tiled engine recounts only the tiles it visits: exact when no
+            # pixel waits, which the lattice ball guarantees
+            for engine in ([1, 0] if not ghost else [1]):
+                u, s, st, r = gpu_fill(img, lab, g, ghost=ghost, tracking=tracking,
+                                       engine=engine, record_fronts=True)
+                hist = r.front_hist.cpu().numpy()
+                np.testing.assert_array_equal(hist[:K], ref.front_hist[0, :K])
+                assert st["max_front"] == ref.max_front
 
 
-def test_max_shells_resume():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_max_shells_resume(engine):
     banner("max_shells resume")
     rng = np.random.default_rng(9)
     img, lab, g = syn.random_tiny(rng, 100, 120, C=3, p_hole=0.5, p_bystander=0.05)
-    u_full, s_full, st_full, _ = gpu_fill(img, lab, g)
+    u_full, s_full, st_full, _ = gpu_fill(img, lab, g, engine=engine)
     assert st_full["K"] >= 4
-    m = 3
-    u1, s1, st1, _ = gpu_fill(img, lab, g, max_shells=m)
+    m = 3 if engine else 5  # 5 is not a multiple of the tiled engine's shells per pass
+    u1, s1, st1, _ = gpu_fill(img, lab, g, max_shells=m, engine=engine)
     assert st1["K"] == m
     lab2 = lab.copy()
     lab2[s1 >= 0] = 0
-    u2, s2, _, _ = gpu_fill(u1.astype(np.float32), lab2, g)
+    u2, s2, _, _ = gpu_fill(u1.astype(np.float32), lab2, g, engine=engine)
     s = np.where(s2 >= 0, s2 + m, s1)
     s = np.where((lab == 1) & (s1 >= 0), s1, s)
     np.testing.assert_array_equal(s, s_full)
     np.testing.assert_array_equal(u2, u_full)
 
 
-def test_fp16_storage():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_fp16_storage(engine):
     import torch
 
     banner("fp16 storage")
@@ -209,7 +252,7 @@ def test_fp16_storage():
     img, lab, g = syn.random_tiny(rng, 150, 170, C=3, p_hole=0.4, p_bystander=0.05)
     img16 = img.astype(np.float16)
     ref = oracle.fill(img16.astype(np.float64), lab, g, storage="f16")
-    u, s, st, _ = gpu_fill(img16.astype(np.float32), lab, g, dtype=torch.float16)
+    u, s, st, _ = gpu_fill(img16.astype(np.float32), lab, g, dtype=torch.float16, engine=engine)
     np.testing.assert_array_equal(s, ref.shell)
     filled = s >= 0
     ulps = f16_ulps(u[filled], ref.u[filled])
@@ -220,18 +263,23 @@ def test_fp16_storage():
 def test_config2_full_size():
     w = syn.config2()
     img, lab, g = w.image[0], w.label[0], w.guide[0]
-    for tracking in (True, False):
-        banner(f"c2 1920x1080 tracking={tracking}")
-        ref, u, s, st, worst = _check(img, lab, g, tracking=tracking)
-        banner(f"c2 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
+    ref = oracle.fill(img, lab, g)
+    for engine in ENGINES:
+        for tracking in (True, False):
+            banner(f"c2 1920x1080 tracking={tracking} engine={engine}")
+            ref, u, s, st, worst = _check(img, lab, g, tracking=tracking, engine=engine, ref=ref)
+            banner(f"c2 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
 
 
 def test_config3_full_size():
     w = syn.config3()
-    banner("c3 3840x2160 eps=5 mu=100")
-    ref, u, s, st, worst = _check(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0)
-    banner(f"c3 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
-    assert st["K"] > 50
+    ref = oracle.fill(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0)
+    for engine in ENGINES:
+        banner(f"c3 3840x2160 eps=5 mu=100 engine={engine}")
+        ref, u, s, st, worst = _check(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0,
+                                      ref=ref, engine=engine)
+        banner(f"c3 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
+        assert st["K"] > 50
 
 
 def test_config4_batched_sampled():
