@@ -113,6 +113,26 @@ template <int G> __device__ inline double gmin(double v) {
 
 __device__ inline int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Wavefront-aggregated appends and counts: one atomic per wavefront instead of
+// one per lane (same-address atomics serialise).  Every lane of the wavefront
+// that is executing must make the call.
+__device__ inline int wave_append(bool want, int *counter) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader, 64);
+    const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
+    return want ? base + rank : -1;
+}
+
+__device__ inline void wave_count(bool pred, int *counter) {
+    const unsigned long long m = __ballot(pred);
+    if (m != 0ull && lane_id() == __ffsll((long long)m) - 1) atomicAdd(counter, (int)__popcll(m));
+}
+
 // readable at shell k: -1 (readable from the start) or filled in a shell < k
 __device__ inline bool readable(int32_t s, int k) { return (unsigned)(s + 1) <= (unsigned)k; }
 

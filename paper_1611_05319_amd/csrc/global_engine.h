@@ -97,8 +97,8 @@ __device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const do
                      A.W, A.H, A.C};
     const float2 gv = reinterpret_cast<const float2 *>(A.guide)[gidx];
     double val[4];
-    if (!fill_core<TS, G>(v, X, Y, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T, k, l,
-                          A.a, A.c, val))
+    if (!fill_core<TS, G>(v, X, Y, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T,
+                          (int)floor(A.eps), k, l, A.a, A.c, val))
         return false;
     if (l == 0) {
         TS *o = reinterpret_cast<TS *>(A.out) + gidx * A.C;

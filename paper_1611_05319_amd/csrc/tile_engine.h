@@ -119,6 +119,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     }
     __syncthreads();
     const int T = s_T;
+    const int Rb = (int)floor(A.eps);
     const int tpf = A.tiles_x * A.tiles_y;  // tiles per frame
     Stage stage{s_stage, &s_stage_n};
     GF_T0();
@@ -301,10 +302,14 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                         if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
                             act |= (st[yy * WW + xx] == S_READABLE);
                     }
-                    if (act) {
-                        st[i] = S_FRONT;
-                        fl[atomicAdd(&s_fn[0], 1)] = (uint16_t)i;
-                    }
+                    if (act) st[i] = S_FRONT;
+                }
+                __syncthreads();
+                for (int base = 0; base < WN; base += kTileBlock) {  // uniform trip count
+                    const int i = base + tid;
+                    const bool want = i < WN && st[i] == S_FRONT;
+                    const int slot = wave_append(want, &s_fn[0]);
+                    if (want) fl[slot] = (uint16_t)i;
                 }
                 __syncthreads();
             }
@@ -312,20 +317,20 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
             LdsView<TS> view{st, col, WW, A.WH, C};
             int cur = 0;
             for (int j = 0; j < Sp; ++j) {
-                auto fill_one = [&](int wi) -> bool {
+                // fill one window pixel with a group; returns ready, sets the counters
+                auto fill_one = [&](int wi, bool &filled_here, bool &interior) -> bool {
                     const int Y = wi / WW, X = wi - Y * WW;
                     const float2 gv = gd[wi];
                     double val[4];
                     const bool ok = fill_core<TS, G>(view, X, Y, (double)gv.x, (double)gv.y,
-                                                     A.ghost != 0, s_off, s_rinv, T, j, l, A.a,
-                                                     A.c, val);
+                                                     A.ghost != 0, s_off, s_rinv, T, Rb, j, l,
+                                                     A.a, A.c, val);
                     if (l == 0) {
-                        if (X >= A.Hh && X < A.Hh + A.TW && Y >= A.Hh && Y < A.Hh + A.TH)
-                            atomicAdd(&s_front_in[j & 31], 1);
+                        interior = X >= A.Hh && X < A.Hh + A.TW && Y >= A.Hh && Y < A.Hh + A.TH;
                         if (ok) {
                             for (int ch = 0; ch < C; ++ch) col[wi * C + ch] = to_storage<TS>(val[ch]);
                             st[wi] = j;
-                            atomicAdd(&s_filled_j, 1);
+                            filled_here = true;
                         }
                     }
                     return ok;
@@ -338,9 +343,11 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                     uint16_t *nlist = fl + (cur ^ 1) * WN;
                     for (int base = 0; base < n; base += nG) {
                         const int item = base + gi;
+                        int push = -1;
+                        bool filled_here = false, interior = false;
                         if (item < n) {
                             const int wi = list[item];
-                            const bool ok = fill_one(wi);
+                            const bool ok = fill_one(wi, filled_here, interior);
                             if (ok) {
                                 if (l < 8) {  // emit unfilled 8-neighbours, CAS dedup
                                     const int d = l < 4 ? l : l + 1;
@@ -349,13 +356,17 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                                     if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH) {
                                         const int nw = yy * WW + xx;
                                         if (st[nw] == S_HOLE && atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
-                                            nlist[atomicAdd(&s_fn[cur ^ 1], 1)] = (uint16_t)nw;
+                                            push = nw;
                                     }
                                 }
                             } else if (l == 0) {
-                                nlist[atomicAdd(&s_fn[cur ^ 1], 1)] = (uint16_t)wi;  // carry over
+                                push = wi;  // not ready: carry over
                             }
                         }
+                        const int slot = wave_append(push >= 0, &s_fn[cur ^ 1]);
+                        if (push >= 0) nlist[slot] = (uint16_t)push;
+                        wave_count(filled_here, &s_filled_j);
+                        wave_count(interior, &s_front_in[j & 31]);
                     }
                 } else {
                     for (int base = 0; base < WN; base += kTileBlock) {
@@ -381,7 +392,10 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                                 if (q == gw) mybit = b;
                             }
                             mask = m2;
-                            if (mybit >= 0) fill_one(base + wave_base + mybit);
+                            bool filled_here = false, interior = false;
+                            if (mybit >= 0) fill_one(base + wave_base + mybit, filled_here, interior);
+                            wave_count(filled_here, &s_filled_j);
+                            wave_count(interior, &s_front_in[j & 31]);
                         }
                     }
                 }
