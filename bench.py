@@ -42,6 +42,42 @@ def algorithmic_bytes(B, H, W, C, elem, n_hole, inplace=False):
     return px * (C * elem + 1 + C * elem + 4) + n_hole * 8
 
 
+def kernel_source_digest():
+    """SHA-256 over the HIP sources (sorted by name): a recorded HBM traffic
+    figure is valid only for the kernel build it was measured on."""
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_1611_05319_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel_prefix):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when it
+    is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2_1080p.md")
+    try:
+        with open(path) as f:
+            rec = dict(line.split(":", 1) for line in f.read().splitlines()
+                       if line.startswith(("source_sha256:", "kernel:", "traffic_bytes_per_launch:")))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256", "").strip() != kernel_source_digest():
+        return None
+    if not rec.get("kernel", "").strip().startswith(kernel_prefix):
+        return None
+    try:
+        return int(float(rec["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, budget_s=10.0):
     """The FP64 oracle, as it stands, on the host cores, on repeated fills of
     the same frame until ~budget_s of CPU time."""
@@ -162,7 +198,8 @@ def main():
                    "shells": st["K"], "max_front": st["max_front"], "parallelism": "none"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None,
+                     "traffic": recorded_traffic("tile_kernel" if params.engine == gf.ENGINE_TILED
+                                                 else "fill_kernel"),
                      "algorithmic_bytes": nbytes, "event_ms_mean": round(ev_mean, 5),
                      "event_ms_median": round(ev_med, 5),
                      "us_per_shell": round(ev_mean * 1e3 / max(st["K"], 1), 3)},

@@ -78,7 +78,8 @@ enum {
     GF_STAT_SHELLS = 0,      /* number of shells that filled at least one pixel (K) */
     GF_STAT_FILLED = 1,      /* pixels filled, all frames */
     GF_STAT_HOLE = 2,        /* label-1 pixels, all frames */
-    GF_STAT_MAX_FRONT = 3,   /* largest active front (lanes requested in one shell) */
+    GF_STAT_MAX_FRONT = 3,   /* largest active front (lanes requested in one shell; the
+                                tiled engine counts as for front_hist below) */
     GF_STAT_LABEL_ERR = 4,   /* label values outside {0, 1, 2} */
     GF_STAT_ORDER_TRUNC = 5, /* 1 if shell_offsets was too short for K + 1 entries */
     GF_STAT_FRAME0 = 8,      /* then per frame f at 8 + 4 f: K_f, filled_f, hole_f, 0 */

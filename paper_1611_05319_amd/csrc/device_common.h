@@ -41,6 +41,7 @@ enum : int {
     G_HOLE = 416,
     G_ERR = 448,
     G_ORDER = 480,  // entries written to order_out
+    G_FRONT = 512,  // [2][32] front sizes per local shell, ring by pass (tiled engine)
 };
 __device__ inline int xw(int x, int field) { return x * kXStride + field; }
 

@@ -152,6 +152,40 @@ bool tile_geometry(const gf_params *p, int C, size_t lds_limit, TileGeom &g) {
     }
 }
 
+// Per (device, kernel, block, dynamic LDS): the dynamic-LDS attribute is set
+// and the occupancy queried once, so a repeated call costs one launch.
+struct LaunchKey {
+    int dev;
+    const void *fn;
+    int block;
+    size_t lds;
+};
+
+int cached_occupancy(int dev, const void *fn, int block, size_t dyn_lds, hipError_t *err) {
+    static std::mutex mu;
+    static LaunchKey keys[256];
+    static int occs[256];
+    static int n = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < n; ++i)
+        if (keys[i].dev == dev && keys[i].fn == fn && keys[i].block == block && keys[i].lds == dyn_lds)
+            return occs[i];
+    *err = hipSuccess;
+    if (dyn_lds > 0) {
+        *err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds);
+        if (*err != hipSuccess) return 0;
+    }
+    int occ = 0;
+    *err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, dyn_lds);
+    if (*err != hipSuccess) return 0;
+    if (occ >= 1 && n < 256) {
+        keys[n] = {dev, fn, block, dyn_lds};
+        occs[n] = occ;
+        ++n;
+    }
+    return occ;
+}
+
 template <typename K>
 gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long long max_blocks,
                       size_t dyn_lds, hipStream_t stream, int block = kBlock) {
@@ -163,17 +197,11 @@ gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long lo
         snprintf(g_last_error, sizeof g_last_error, "device %d has no cooperative launch", dev);
         return GF_EUNSUPPORTED;
     }
-    if (dyn_lds > 0) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds);
-        if (e != hipSuccess) { set_err("hipFuncSetAttribute", e); return GF_EDEVICE; }
-    }
-    int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(kernel),
-                                                     block, dyn_lds);
+    e = hipSuccess;
+    const int occ = cached_occupancy(dev, reinterpret_cast<const void *>(kernel), block, dyn_lds, &e);
     if (e != hipSuccess || occ < 1) {
         if (e == hipSuccess) snprintf(g_last_error, sizeof g_last_error, "kernel does not fit a CU");
-        else set_err("occupancy", e);
+        else set_err("launch set-up", e);
         return GF_EDEVICE;
     }
     int per_cu = blocks_per_cu > 0 ? blocks_per_cu : (block > kBlock ? 1 : 2);

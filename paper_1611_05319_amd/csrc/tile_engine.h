@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     // ---- passes of S shells -------------------------------------------------
     const int total_hole = sum_x(ctl, XF_HOLE);
     long long total_filled = 0;
+    int max_front = 0;  // kept by thread 0 of logical workgroup 0
     const int nG = kTileBlock / G;
     const int gi = tid / G, l = tid & (G - 1);
     const int wave_base = tid & ~63;
@@ -444,9 +445,11 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                         s_pass_fill += tf;
                         s_pass_kmax = max(s_pass_kmax, s_r[2]);
                     }
-                    if (A.front_hist)
-                        for (int j = 0; j < Sp && j < 32; ++j)
-                            if (s_front_in[j] && k0 + j < A.kcap) atomicAdd(&A.front_hist[k0 + j], s_front_in[j]);
+                    for (int j = 0; j < Sp && j < 32; ++j) {
+                        if (!s_front_in[j]) continue;
+                        atomicAdd(&ctl[G_FRONT + (p & 1) * 32 + j], s_front_in[j]);
+                        if (A.front_hist && k0 + j < A.kcap) atomicAdd(&A.front_hist[k0 + j], s_front_in[j]);
+                    }
                 }
                 if (tf && A.tile_track && tid < 9) {  // the 3 x 3 tile neighbourhood may change next pass
                     const int nx = tx + tid % 3 - 1, ny = ty + tid / 3 - 1;
@@ -472,6 +475,13 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
         GF_TACC(5);
         GF_TCNT(10, 1);
         const int fills = sum_x(ctl, XF_PFILL + p % 3);
+        if (lw == 0 && tid == 0) {  // front sizes of the pass; the half is reused two passes on
+            for (int j = 0; j < Sp && j < 32; ++j) {
+                int32_t *cw = &ctl[G_FRONT + (p & 1) * 32 + j];
+                max_front = max(max_front, ld_ctl(ctl, G_FRONT + (p & 1) * 32 + j));
+                __hip_atomic_store(cw, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (fills == 0) break;
         total_filled += fills;
     }
@@ -510,14 +520,10 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
         __syncthreads();
     }
     if (lw == 0 && tid == 0) {
-        const int K = max_x(ctl, XF_KMAX);
-        int mf = 0;
-        if (A.front_hist)
-            for (int k = 0; k < K && k < A.kcap; ++k) mf = max(mf, A.front_hist[k]);
-        A.stats[0] = K;
+        A.stats[0] = max_x(ctl, XF_KMAX);
         A.stats[1] = (int32_t)total_filled;
         A.stats[2] = total_hole;
-        A.stats[3] = mf;
+        A.stats[3] = max_front;
         A.stats[4] = sum_x(ctl, XF_ERR);
         A.stats[5] = 0;
     }

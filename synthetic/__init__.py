@@ -392,10 +392,12 @@ def _map_frames(fn, jobs, workers):
         workers = min(len(jobs), os.cpu_count() or 1, 16)
     if workers <= 1 or len(jobs) <= 1:
         return [fn(j) for j in jobs]
-    import multiprocessing as mp
+    # threads, not processes: the array work releases the GIL, and nothing is
+    # forked from a process that may already drive a GPU
+    from concurrent.futures import ThreadPoolExecutor
 
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(fn, jobs)
+    with ThreadPoolExecutor(workers) as pool:
+        return list(pool.map(fn, jobs))
 
 
 def config4(seed: int = 4, B: int = 64, H: int = 1080, W: int = 1920,
