@@ -64,12 +64,14 @@ typedef struct {
     int32_t tracking;    /* 1: lanes for the tracked front only; 0: one lane per pixel per shell */
     int32_t max_shells;  /* 0: run until no pixel is ready; n > 0: stop after n shells */
     int32_t engine;      /* gf_engine */
-    int32_t group;       /* lanes per pixel: 0 (auto), 8 (tiled engine), 16, 32 or 64 */
+    int32_t group;       /* lanes per pixel: 8, 16, 32 or 64; 0 = the smallest with at most
+                            4 ball offsets per lane */
     int32_t blocks_per_cu; /* persistent workgroups per compute unit: 0 (auto) or 1..8 */
     int32_t tile_w, tile_h; /* tiled engine: tile interior in pixels, 0 = auto (<= 256) */
     int32_t pass_shells;    /* tiled engine: shells per grid sync, 0 = auto (<= 32); the halo
                                pass_shells * ceil(eps) may not exceed tile_w or tile_h */
-    int32_t reserved;
+    int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (auto), 256, 512 or 1024;
+                               must be 0 with GF_ENGINE_FRONT */
 } gf_params;
 
 /* Layout of the int32 stats array written by gf_fill / gf_fill_batched

@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
                 ("max_shells", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("pass_shells", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("pass_shells", ctypes.c_int32), ("tile_threads", ctypes.c_int32)]
 
 
 @dataclass
@@ -68,12 +68,13 @@ class Params:
     tile_w: int = 0
     tile_h: int = 0
     pass_shells: int = 0
+    tile_threads: int = 0
 
     def c_struct(self) -> _Params:
         return _Params(float(self.eps), float(self.mu), float(self.c), int(bool(self.ghost)),
                        int(bool(self.tracking)), int(self.max_shells), int(self.engine),
                        int(self.group), int(self.blocks_per_cu), int(self.tile_w),
-                       int(self.tile_h), int(self.pass_shells), 0)
+                       int(self.tile_h), int(self.pass_shells), int(self.tile_threads))
 
 
 def library_path() -> str:

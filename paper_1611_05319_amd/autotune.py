@@ -1,0 +1,180 @@
+"""Launch-shape autotuner for the shell fill.
+
+The best engine and launch shape depend on the hole: thin bands with a few
+shells favour the tiled engine (LDS windows, several shells per grid sync),
+deep fronts with many shells can favour one grid sync per shell, and the tile
+size, shells per pass (which fix the LDS halo, pass_shells * ceil(eps)),
+lanes per pixel and workgroups per compute unit trade parallelism against
+redundant halo work.  `tune` times a small candidate set on the caller's own
+device buffers (out of place, so the inputs are not touched), picks the
+fastest by median HIP-event time, and remembers the choice per problem key in
+a JSON cache.
+
+    params = tune(img, label, guide, Params(eps=3, mu=50))
+    plan = FillPlan(img, label, guide, params)
+
+Only launch-shape fields are tuned (engine, group, blocks_per_cu, tile_w,
+tile_h, pass_shells, tile_threads); every candidate computes the same fill (the shell map
+bit for bit; colours up to the summation order of the lanes).
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import tempfile
+import threading
+from dataclasses import asdict
+
+import torch
+
+from . import ENGINE_FRONT, ENGINE_TILED, FillPlan, Params, library_path, tile_geometry
+
+_TUNED = ("engine", "group", "blocks_per_cu", "tile_w", "tile_h", "pass_shells", "tile_threads")
+_lock = threading.Lock()
+
+
+def cache_path() -> str:
+    p = os.environ.get("GF_AUTOTUNE_CACHE")
+    if p:
+        return p
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "paper_1611_05319_amd", "autotune.json")
+
+
+def _library_digest() -> str:
+    h = hashlib.sha256()
+    with open(library_path(), "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()[:16]
+
+
+def problem_key(img: torch.Tensor, label: torch.Tensor, params: Params) -> str:
+    """Shape, storage type, method parameters, device and library build.  The
+    hole fraction (to 1 %) stands in for the hole's structure."""
+    if img.dim() == 3:
+        img, label = img.unsqueeze(0), label.unsqueeze(0)
+    B, H, W, C = img.shape
+    frac = float((label == 1).sum().item()) / float(B * H * W)
+    dev = torch.cuda.get_device_properties(img.device)
+    order = "smart" if params.c >= 0 else "onion"
+    return (f"{B}x{H}x{W}x{C}:{str(img.dtype).replace('torch.', '')}:eps={params.eps:g}:"
+            f"mu={params.mu:g}:{order}:ghost={int(bool(params.ghost))}:"
+            f"track={int(bool(params.tracking))}:hole={round(100 * frac)}%:"
+            f"{dev.name}:{dev.multi_processor_count}cu:lib={_library_digest()}")
+
+
+def candidates(img: torch.Tensor, params: Params) -> list[Params]:
+    """Launch shapes worth timing for this problem (all valid on the device)."""
+    if img.dim() == 3:
+        img = img.unsqueeze(0)
+    _, H, W, C = img.shape
+    base = {k: v for k, v in asdict(params).items() if k not in _TUNED}
+    out: list[Params] = []
+    seen = set()
+
+    def add(**kw):
+        p = Params(**base, **kw)
+        key = tuple(getattr(p, k) for k in _TUNED)
+        if key in seen:
+            return
+        if p.engine == ENGINE_TILED:
+            try:
+                tile_geometry(H, W, C, img.dtype, p)
+            except RuntimeError:
+                return  # the window does not fit the LDS, or the halo exceeds the tile
+        seen.add(key)
+        out.append(p)
+
+    rd = int(-(-params.eps // 1))  # ceil(eps): halo per shell
+    add(engine=ENGINE_TILED)  # the library's own choice first
+    for S in (2, 3, 4, 6):
+        for tile in (16, 24, 32, 48):
+            if S * rd <= tile:
+                add(engine=ENGINE_TILED, tile_w=tile, tile_h=tile, pass_shells=S)
+    add(engine=ENGINE_TILED, group=16)
+    # 512-thread workgroups: twice the registers per lane of the 1024-thread form
+    for S in (2, 3, 4, 6):
+        for tile in (24, 32, 48):
+            if S * rd <= tile:
+                add(engine=ENGINE_TILED, tile_threads=512, tile_w=tile, tile_h=tile, pass_shells=S)
+    # small workgroups: several windows per compute unit
+    for S in (1, 2, 3, 4):
+        for tile in (8, 12, 16, 24, 32):
+            if S * rd <= tile:
+                add(engine=ENGINE_TILED, tile_threads=256, tile_w=tile, tile_h=tile, pass_shells=S)
+    add(engine=ENGINE_FRONT)
+    for g in (16, 32, 64):
+        for bpc in (0, 1, 4):
+            add(engine=ENGINE_FRONT, group=g, blocks_per_cu=bpc)
+    return out
+
+
+def _time(plan: FillPlan, reps: int) -> float:
+    plan.run()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        plan.run()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in ev)
+    return ts[len(ts) // 2]
+
+
+def _load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path: str, key: str, entry: dict) -> None:
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    d = _load_cache(path)
+    d[key] = entry
+    fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path) or ".", prefix=".autotune")
+    with os.fdopen(fd, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
+         params: Params | None = None, *, reps: int = 5, use_cache: bool = True,
+         path: str | None = None, report: list | None = None) -> Params:
+    """Fastest launch shape for filling these buffers with `params`'s method
+    parameters.  `report`, if given, receives (params, median ms) per
+    candidate timed."""
+    params = params or Params()
+    path = path or cache_path()
+    key = problem_key(img, label, params)
+    with _lock:
+        if use_cache:
+            hit = _load_cache(path).get(key)
+            if hit:
+                return Params(**{**asdict(params), **{k: hit["params"][k] for k in _TUNED}})
+        best, best_ms = None, float("inf")
+        for p in candidates(img, params):
+            try:
+                plan = FillPlan(img, label, guide, p)
+                ms = _time(plan, reps)
+            except RuntimeError:
+                continue  # not launchable on this device (e.g. does not fit a CU)
+            finally:
+                plan = None
+            if report is not None:
+                report.append((p, ms))
+            if ms < best_ms:
+                best, best_ms = p, ms
+        if best is None:
+            raise RuntimeError("no launch shape could be timed")
+        if use_cache:
+            _store_cache(path, key, {"params": {k: getattr(best, k) for k in _TUNED},
+                                     "ms": best_ms})
+        return best

@@ -15,6 +15,7 @@ namespace gfk {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
 constexpr int kMaxOffsets = 256;  // eps <= 9: 252 offsets
+constexpr int kPadOffset = 16384; // (n, m) of the padding entries of the offset table
 constexpr int kPerLaneMax = 4;    // ball offsets handled by one lane
 constexpr int kStageCap = 2048;   // LDS staging entries per workgroup
 constexpr int kFrameCap = 64;     // frames with LDS statistics accumulators (global engine)
@@ -42,8 +43,33 @@ enum : int {
     G_ERR = 448,
     G_ORDER = 480,  // entries written to order_out
     G_FRONT = 512,  // [2][32] front sizes per local shell, ring by pass (tiled engine)
+    G_COPY = 640,   // next chunk of the deferred out-of-place copy (tiled engine)
 };
 __device__ inline int xw(int x, int field) { return x * kXStride + field; }
+
+// Optional timing hooks (compiled in only with -DGF_TRACE, for profiling
+// builds): per-workgroup accumulators of wall-clock ticks and counts.
+#ifdef GF_TRACE
+constexpr int kTraceSlots = 16;
+__device__ long long gf_trace[4096 * kTraceSlots];
+#define GF_T0() long long gf_t_last = wall_clock64()
+#define GF_TACC(slot)                                                                   \
+    do {                                                                                \
+        if (threadIdx.x == 0) {                                                         \
+            const long long gf_t_now = wall_clock64();                                  \
+            gf_trace[blockIdx.x * kTraceSlots + (slot)] += gf_t_now - gf_t_last;        \
+            gf_t_last = gf_t_now;                                                       \
+        }                                                                               \
+    } while (0)
+#define GF_TCNT(slot, v)                                                                \
+    do {                                                                                \
+        if (threadIdx.x == 0) gf_trace[blockIdx.x * kTraceSlots + (slot)] += (v);       \
+    } while (0)
+#else
+#define GF_T0()
+#define GF_TACC(slot)
+#define GF_TCNT(slot, v)
+#endif
 
 // shell-map and window codes
 constexpr int32_t S_READABLE = -1;
@@ -223,6 +249,12 @@ __device__ void build_offsets(double eps, short2 *off, double *rinv, int *T) {
                 ++cnt;
             }
         *T = cnt < kMaxOffsets ? cnt : kMaxOffsets;
+        // padding up to the table size: far outside any image or window (never
+        // readable) and of weight 0, so a group reads G * lanes entries unchecked
+        for (int t = cnt; t < kMaxOffsets; ++t) {
+            off[t] = make_short2((short)kPadOffset, (short)kPadOffset);
+            rinv[t] = 0.0;
+        }
     }
 }
 

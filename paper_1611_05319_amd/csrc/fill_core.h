@@ -4,13 +4,24 @@
 // with onion order or the smart-order test (Sec. 3.4, eqn:confidence,
 // eqn:ready).  The state and colours are read through a view: the frame in
 // global memory, or a tile window staged in LDS.
+//
+// Precision: every quantity that decides a shell (the ghost offsets, their
+// floors and lattice-line tests, the smart-order confidence) is FP64 with no
+// contraction, as the reference computes it.  The weights and the weighted
+// sum are FP64; the bilinear value of one ghost point is interpolated in FP32
+// from the stored (binary32 / binary16) colours, exact on lattice lines and
+// for constant data.
 #pragma once
 
 #include "device_common.h"
 
 namespace gfk {
 
-// frame in global memory (state = shell map)
+// colours as FP32
+__device__ inline float px_f32(float v) { return v; }
+__device__ inline float px_f32(__half v) { return __half2float(v); }
+
+// frame in global memory (state = shell map; colours C per pixel, unpadded)
 template <typename TS> struct GlobalView {
     const int32_t *S;
     const TS *U;
@@ -21,40 +32,88 @@ template <typename TS> struct GlobalView {
     __device__ int index(int x, int y) const { return y * W + x; }
     __device__ int pitch() const { return W; }
     __device__ int32_t state_at(int i) const { return S[i]; }
-    __device__ double colour_at(int i, int c) const { return load_px(U + (long long)i * C + c); }
+    __device__ void colours(int i, float o[4]) const {
+        const TS *p = U + (long long)i * C;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) o[ch] = ch < C ? px_f32(p[ch]) : 0.0f;
+    }
 };
 
+// channels of a pixel in an LDS window: 3 are padded to 4 for vector loads
+__host__ __device__ inline int padded_channels(int C) { return C == 3 ? 4 : C; }
+
+template <typename TS> __device__ inline void lds_colours(const TS *p, int CP, float o[4]);
+template <> __device__ inline void lds_colours<float>(const float *p, int CP, float o[4]) {
+    if (CP == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    } else if (CP == 2) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = 0.0f; o[3] = 0.0f;
+    } else {
+        o[0] = p[0]; o[1] = 0.0f; o[2] = 0.0f; o[3] = 0.0f;
+    }
+}
+template <> __device__ inline void lds_colours<__half>(const __half *p, int CP, float o[4]) {
+    if (CP == 4) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        o[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
+        o[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
+        o[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
+        o[3] = __half2float(__ushort_as_half((unsigned short)(v.y >> 16)));
+    } else if (CP == 2) {
+        const unsigned v = *reinterpret_cast<const unsigned *>(p);
+        o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
+        o[1] = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
+        o[2] = 0.0f; o[3] = 0.0f;
+    } else {
+        o[0] = __half2float(p[0]); o[1] = 0.0f; o[2] = 0.0f; o[3] = 0.0f;
+    }
+}
+
 // tile window in LDS (state = window codes; pixels outside the frame are
-// bystander-coded, so they are never readable)
+// bystander-coded, so they are never readable); CP channels per pixel
 template <typename TS> struct LdsView {
     const int32_t *st;
     const TS *col;
-    int WW, WH, C;
+    int WW, WH, C, CP;
     __device__ bool inside(int x0, int y0, int x1, int y1) const {
         return x0 >= 0 && y0 >= 0 && x1 < WW && y1 < WH;
     }
     __device__ int index(int x, int y) const { return y * WW + x; }
     __device__ int pitch() const { return WW; }
     __device__ int32_t state_at(int i) const { return st[i]; }
-    __device__ double colour_at(int i, int c) const { return load_px(col + i * C + c); }
+    __device__ void colours(int i, float o[4]) const { lds_colours<TS>(col + i * CP, CP, o); }
 };
+
+template <int G> __device__ inline int gmin_i(int v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
+    return v;
+}
 
 // Weights are exp(-(q - q_min)) / |(n, m)|: relative to the largest readable
 // weight (the quotient is unchanged, nothing underflows), with the exact
 // distance of the unrotated offset.  With the rotated ball the exponent is
 // q = a |g|^2 n^2 (g_perp . R(n, m) = -|g| n), so it takes at most R + 1
 // values: lane |n| of the group evaluates exp once and the others read it by
-// a shuffle.
+// a shuffle; q_min is a |g|^2 times the smallest readable n^2.  The lattice
+// ball (no ghost pixels, or g = 0) evaluates exp per offset; that code runs
+// only in wavefronts that hold such a pixel.
+// The per-offset work is branch-free: the offset table is padded with entries
+// that are never readable and weigh 0, unreadable points contribute through
+// selects, and every load stays inside the view.
 // Returns true (on every lane of the group) when the pixel is ready; then
 // out[0..C) holds its new colour (FP64, before storage rounding).
 // (X, Y): the pixel in the view's coordinates; k: the shell used by the
 // readable test (s in [-1, k-1]); a = mu^2 / (2 eps^2); c < 0: onion order;
-// R = floor(eps) < G.
+// R = floor(eps) < G; off / rinv: the padded offset table (4 G entries).
 template <typename TS, int G, typename V>
 __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool ghost,
                           const short2 *off, const double *rinv, int T, int R, int k, int l,
                           double a, double c, double out[4]) {
     const bool rot = ghost && (gx != 0.0 || gy != 0.0);
+    const bool lattice_here = __any(!rot);  // wavefront-uniform
     const double L2 = gx * gx + gy * gy;
     double cs = 0.0, sn = 0.0;
     if (rot) {
@@ -63,73 +122,81 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         sn = gy / L;
     }
     const double aL2 = a * L2;
-    // pass 1: readable set, exponents, bilinear supports (kept for pass 2)
-    double q[kPerLaneMax], fxs[kPerLaneMax], fys[kPerLaneMax];
-    int base[kPerLaneMax];
+    const int P = v.pitch();
+    // pass 1: readable set and bilinear supports (kept for pass 2)
+    float fxs[kPerLaneMax], fys[kPerLaneMax];
+    int base[kPerLaneMax], an[kPerLaneMax];
     unsigned rmask = 0, exmask = 0, eymask = 0;
-    double qmin_r = INFINITY, qmin_all = INFINITY;
+    int n2min = 0x7fffffff;    // rotated ball: smallest readable n^2
+    double qmin_r = INFINITY;  // lattice ball: smallest readable exponent
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
-        q[r] = INFINITY;
-        fxs[r] = 0.0;
-        fys[r] = 0.0;
-        base[r] = 0;
         const int t = l + r * G;
-        if (t < T) {
-            const short2 nm = off[t];
-            double ox, oy;
-            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
-            const double fx0 = floor(ox), fy0 = floor(oy);
-            const bool ex = (ox == fx0), ey = (oy == fy0);
-            const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
-            const int x1 = x0 + (ex ? 0 : 1), y1 = y0 + (ey ? 0 : 1);
-            fxs[r] = ox - fx0;
-            fys[r] = oy - fy0;
-            exmask |= ex ? (1u << r) : 0u;
-            eymask |= ey ? (1u << r) : 0u;
-            bool rd = false;
-            if (v.inside(x0, y0, x1, y1)) {
-                const int b = v.index(x0, y0), P = v.pitch();
-                base[r] = b;
-                const int dx = ex ? 0 : 1, dy = ey ? 0 : P;
-                const int32_t a0 = v.state_at(b), a1 = v.state_at(b + dx);
-                const int32_t a2 = v.state_at(b + dy), a3 = v.state_at(b + dy + dx);
-                rd = ((int)readable(a0, k) & (int)readable(a1, k) & (int)readable(a2, k) &
-                      (int)readable(a3, k)) != 0;
-            }
-            if (rot) {
-                q[r] = aL2 * (double)(nm.x * nm.x);
-            } else {
-                const double tp = (-gy) * ox + gx * oy;
-                q[r] = a * tp * tp;
-            }
-            qmin_all = fmin(qmin_all, q[r]);
-            if (rd) {
-                rmask |= 1u << r;
-                qmin_r = fmin(qmin_r, q[r]);
-            }
+        const short2 nm = off[t];
+        double ox, oy;
+        rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+        const double fx0 = floor(ox), fy0 = floor(oy);
+        const bool ex = (ox == fx0), ey = (oy == fy0);
+        const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
+        const int x1 = x0 + (ex ? 0 : 1), y1 = y0 + (ey ? 0 : 1);
+        fxs[r] = (float)(ox - fx0);
+        fys[r] = (float)(oy - fy0);
+        const bool ins = v.inside(x0, y0, x1, y1);
+        const int b = ins ? v.index(x0, y0) : 0;
+        const int dx = (ex || !ins) ? 0 : 1, dy = (ey || !ins) ? 0 : P;
+        const int32_t a0 = v.state_at(b), a1 = v.state_at(b + dx);
+        const int32_t a2 = v.state_at(b + dy), a3 = v.state_at(b + dy + dx);
+        const bool rd = ins && (((int)readable(a0, k) & (int)readable(a1, k) &
+                                 (int)readable(a2, k) & (int)readable(a3, k)) != 0);
+        base[r] = b;
+        an[r] = abs((int)nm.x);
+        rmask |= rd ? (1u << r) : 0u;
+        exmask |= (ex || !rd) ? (1u << r) : 0u;  // unreadable points read one pixel
+        eymask |= (ey || !rd) ? (1u << r) : 0u;
+        n2min = min(n2min, rd ? an[r] * an[r] : 0x7fffffff);
+        if (lattice_here) {
+            const double tp = (-gy) * ox + gx * oy;
+            qmin_r = fmin(qmin_r, rd ? a * tp * tp : INFINITY);
         }
     }
-    qmin_r = gmin<G>(qmin_r);
-    if (!(qmin_r < INFINITY)) return false;  // no readable point: the pixel waits
-    // exponentials: shared by |n| with the rotated ball, one per offset otherwise
-    double e_r = 0.0, e_all = 0.0;
-    if (rot && l <= R) {
-        e_r = exp(-(aL2 * (double)(l * l) - qmin_r));
-        e_all = exp(-(aL2 * (double)(l * l)));  // q_min over the whole ball is 0 (n = 0)
+    // exponentials of the readable weights
+    n2min = gmin_i<G>(n2min);
+    if (lattice_here) qmin_r = gmin<G>(qmin_r);
+    if (rot) {
+        if (n2min == 0x7fffffff) return false;  // no readable point: the pixel waits
+        qmin_r = aL2 * (double)n2min;
+    } else if (!(qmin_r < INFINITY)) {
+        return false;
     }
-    if (c >= 0.0) {  // smart order
-        if (!rot) qmin_all = gmin<G>(qmin_all);
+    const double e_r = exp(-(aL2 * (double)(l * l) - qmin_r));  // used by lanes l <= R
+    if (c >= 0.0) {  // smart order: confidence over the whole ball, shifted by its q_min
+        double e_all = 0.0, qmin_all = 0.0;  // rotated ball: q_min over the ball is 0 (n = 0)
+        if (rot) {
+            if (l <= R) e_all = exp(-(aL2 * (double)(l * l)));
+        } else {
+            double qm = INFINITY;
+#pragma unroll
+            for (int r = 0; r < kPerLaneMax; ++r) {
+                const int t = l + r * G;
+                if (t < T) {
+                    const short2 nm = off[t];
+                    const double tp = (-gy) * (double)nm.x + gx * (double)nm.y;
+                    qm = fmin(qm, a * tp * tp);
+                }
+            }
+            qmin_all = gmin<G>(qm);
+        }
         double num = 0.0, den = 0.0;
 #pragma unroll
         for (int r = 0; r < kPerLaneMax; ++r) {
             const int t = l + r * G;
+            const short2 nm = off[t];
             double w = 0.0;
             if (rot) {
-                const int an = t < T ? abs((int)off[t].x) : 0;
-                w = __shfl(e_all, an, G) * (t < T ? rinv[t] : 0.0);
+                w = __shfl(e_all, t < T ? an[r] : 0, G) * rinv[t];
             } else if (t < T) {
-                w = exp(-(q[r] - qmin_all)) * rinv[t];
+                const double tp = (-gy) * (double)nm.x + gx * (double)nm.y;
+                w = exp(-(a * tp * tp - qmin_all)) * rinv[t];
             }
             den += w;
             if (rmask & (1u << r)) num += w;
@@ -140,31 +207,36 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     }
     // pass 2: weighted average of the readable ghost values
     double Ssum = 0.0, acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int C = v.C, P = v.pitch();
+    const int C = v.C;
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
         const int t = l + r * G;
-        double w = 0.0;
-        if (rot) {  // every lane takes part in the shuffle
-            const int an = t < T ? abs((int)off[t].x) : 0;
-            w = __shfl(e_r, an, G);
+        double e = __shfl(e_r, an[r] & (G - 1), G);  // every lane takes part
+        if (lattice_here && !rot) {
+            const short2 nm = off[t];
+            const double tp = (-gy) * (double)nm.x + gx * (double)nm.y;
+            e = exp(-(a * tp * tp - qmin_r));
         }
-        if (rmask & (1u << r)) {
-            w = (rot ? w : exp(-(q[r] - qmin_r))) * rinv[t];
-            Ssum += w;
-            const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-            const double wx1 = ex ? 0.0 : fxs[r], wy1 = ey ? 0.0 : fys[r];
-            const double wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
-            const double b00 = wx0 * wy0, b10 = wx1 * wy0, b01 = wx0 * wy1, b11 = wx1 * wy1;
-            const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : P),
-                      i11 = i01 + (ex ? 0 : 1);
+        const bool rd = (rmask >> r) & 1u;
+        const double w = rd ? e * rinv[t] : 0.0;
+        Ssum += w;
+        const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
+        const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : P),
+                  i11 = i01 + (ex ? 0 : 1);
+        float c00[4], c10[4], c01[4], c11[4];
+        v.colours(i00, c00);
+        v.colours(i10, c10);
+        v.colours(i01, c01);
+        v.colours(i11, c11);
+        const float fx = fxs[r], fy = fys[r];
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                if (ch < C) {
-                    const double val = b00 * v.colour_at(i00, ch) + b10 * v.colour_at(i10, ch) +
-                                       b01 * v.colour_at(i01, ch) + b11 * v.colour_at(i11, ch);
-                    acc[ch] += w * val;
-                }
+        for (int ch = 0; ch < 4; ++ch) {
+            if (ch < C) {
+                const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
+                const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
+                const float val = fmaf(fy, bot - top, top);
+                // an unreadable point may hold any bits (even NaN): select, do not scale
+                acc[ch] = rd ? fma(w, (double)val, acc[ch]) : acc[ch];
             }
         }
     }

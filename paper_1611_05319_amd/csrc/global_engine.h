@@ -35,15 +35,18 @@ struct FillArgs {
     int ghost;
 };
 
+constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
+
 // LDS staging of list appends: one global atomic per workgroup per flush
 struct Stage {
     int *buf;
     int *n;
+    int cap;  // entries of buf
 };
 
 __device__ inline void stage_push(Stage st, int v, int32_t *glist, int32_t *gcount) {
     int slot = atomicAdd(st.n, 1);
-    if (slot < kStageCap) {
+    if (slot < st.cap) {
         st.buf[slot] = v;
     } else {  // LDS full: append directly
         int pos = atomicAdd(gcount, 1);
@@ -54,7 +57,7 @@ __device__ inline void stage_push(Stage st, int v, int32_t *glist, int32_t *gcou
 __device__ inline void stage_flush(Stage st, int32_t *glist, int32_t *gcount, int *s_base) {
     __syncthreads();
     int n = *st.n;
-    if (n > kStageCap) n = kStageCap;
+    if (n > st.cap) n = st.cap;
     if (threadIdx.x == 0) *s_base = n ? atomicAdd(gcount, n) : 0;
     __syncthreads();
     const int base = *s_base;
@@ -89,13 +92,12 @@ __device__ inline void copy_range(const char *src, char *dst, size_t b0, size_t 
 
 template <typename TS, int G>
 __device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const double *rinv, int T,
-                                  long long gidx, int k, int l) {
+                                  long long gidx, float2 gv, int k, int l) {
     const long long f = gidx / A.HW;
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
     GlobalView<TS> v{A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
                      A.W, A.H, A.C};
-    const float2 gv = reinterpret_cast<const float2 *>(A.guide)[gidx];
     double val[4];
     if (!fill_core<TS, G>(v, X, Y, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T,
                           (int)floor(A.eps), k, l, A.a, A.c, val))
@@ -119,6 +121,8 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
     __shared__ int s_ord_n;
     __shared__ int s_fill_n, s_active_n, s_hole_n, s_err_n;
     __shared__ int s_base;
+    __shared__ int s_item[kItemCap];    // this shell's list entries of the workgroup
+    __shared__ float2 s_gd[kItemCap];   // and their guides
     __shared__ int s_frame_fill[kFrameCap];
     __shared__ int s_frame_k[kFrameCap];
     __shared__ int s_frame_hole[kFrameCap];
@@ -139,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
     int32_t *ctl = A.ctl;
     const int W = A.W, H = A.H;
     const bool track = A.tracking != 0;
+    GF_T0();
 
     // ---- init: copy, shell codes, hole count, shell-0 front ----------------
     {
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
             copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
                        (size_t)lo * esz, (size_t)hi * esz);
         }
-        Stage st{s_list, &s_list_n};
+        Stage st{s_list, &s_list_n, kStageCap};
         for (long long p = lo + tid; p < hi; p += kBlock) {
             const uint8_t lab = A.label[p];
             int32_t code;
@@ -190,7 +195,9 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
         for (int i = tid; i < kFrameCap && i < A.B; i += kBlock)
             if (s_frame_hole[i]) atomicAdd(&A.stats[8 + 4 * i + 2], s_frame_hole[i]);
     }
+    GF_TACC(0);
     grid_sync(ctl, (unsigned)nblk);
+    GF_TACC(3);
 
     // ---- shells -------------------------------------------------------------
     const int total_hole = sum_x(ctl, XF_HOLE);
@@ -199,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
     const int nG = kBlock / G;
     const int gi = tid / G;       // group within the workgroup
     const int l = tid & (G - 1);  // lane within the group
-    Stage lst{s_list, &s_list_n};
-    Stage ord{s_ord, &s_ord_n};
+    Stage lst{s_list, &s_list_n, kStageCap};
+    Stage ord{s_ord, &s_ord_n, kStageCap};
     const bool want_order = A.order != nullptr;
     int nk = ld_ctl(ctl, G_LIST + 0);
     for (int k = 0; total_filled < total_hole; ++k) {
@@ -230,28 +237,42 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
         if (track) {
             const int32_t *cur = (k & 1) ? A.listB : A.listA;
             const long long lo = (long long)nk * lw / nblk, hi = (long long)nk * (lw + 1) / nblk;
-            for (long long base = lo; base < hi; base += nG) {
-                const long long item = base + gi;
-                if (item < hi) {
-                    const long long gidx = cur[item];
-                    const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, k, l);
-                    const long long f = gidx / A.HW;
-                    const int p = (int)(gidx - f * A.HW);
-                    if (ok) {
-                        if (l < 8) {  // emit the unfilled 8-neighbours (dedup by CAS on the map)
-                            const int d = l < 4 ? l : l + 1;
-                            const int y = p / W, x = p - y * W;
-                            const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
-                            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
-                                int32_t *sp = A.shell + f * A.HW + (long long)yy * W + xx;
-                                if (*sp == S_HOLE && atomicCAS(sp, S_HOLE, S_FRONT) == S_HOLE)
-                                    stage_push(lst, (int)(f * A.HW + (long long)yy * W + xx),
-                                               nxt_list, nxt_cnt);
+            // this workgroup's items and their guides are staged in LDS first, so
+            // the rounds of groups start from LDS instead of two dependent loads
+            for (long long c0 = lo; c0 < hi; c0 += kItemCap) {
+                const int cn = (int)min((long long)kItemCap, hi - c0);
+                __syncthreads();  // the previous chunk's readers are done
+                for (int i = tid; i < cn; i += kBlock) {
+                    const int gidx = cur[c0 + i];
+                    s_item[i] = gidx;
+                    s_gd[i] = reinterpret_cast<const float2 *>(A.guide)[gidx];
+                }
+                __syncthreads();
+                for (int base = 0; base < cn; base += nG) {
+                    const int item = base + gi;
+                    GF_TCNT(8, 1);
+                    if (item < cn) {
+                        const long long gidx = s_item[item];
+                        const bool ok =
+                            global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l);
+                        const long long f = gidx / A.HW;
+                        const int p = (int)(gidx - f * A.HW);
+                        if (ok) {
+                            if (l < 8) {  // emit the unfilled 8-neighbours (dedup by CAS on the map)
+                                const int d = l < 4 ? l : l + 1;
+                                const int y = p / W, x = p - y * W;
+                                const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
+                                if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                                    int32_t *sp = A.shell + f * A.HW + (long long)yy * W + xx;
+                                    if (*sp == S_HOLE && atomicCAS(sp, S_HOLE, S_FRONT) == S_HOLE)
+                                        stage_push(lst, (int)(f * A.HW + (long long)yy * W + xx),
+                                                   nxt_list, nxt_cnt);
+                                }
                             }
+                            if (l == 0) on_filled(gidx);
+                        } else if (l == 0) {
+                            stage_push(lst, (int)gidx, nxt_list, nxt_cnt);  // not ready: carry over
                         }
-                        if (l == 0) on_filled(gidx);
-                    } else if (l == 0) {
-                        stage_push(lst, (int)gidx, nxt_list, nxt_cnt);  // not ready: carry over
                     }
                 }
             }
@@ -289,12 +310,14 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
                     mask = m2;
                     if (mybit >= 0) {
                         const long long px = base + wave_base + mybit;
-                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, k, l);
+                        const float2 gv = reinterpret_cast<const float2 *>(A.guide)[px];
+                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, gv, k, l);
                         if (ok && l == 0) on_filled(px);
                     }
                 }
             }
         }
+        GF_TACC(1);
         if (my_fill) atomicAdd(&s_fill_n, my_fill);
         if (track) stage_flush(lst, nxt_list, nxt_cnt, &s_base);
         if (want_order) stage_flush(ord, A.order, &ctl[G_ORDER], &s_base);
@@ -305,8 +328,13 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
             s_fill_n = 0;
             s_active_n = 0;
         }
+        GF_TACC(2);
         grid_sync(ctl, (unsigned)nblk);
+        GF_TACC(3);
+        GF_TCNT(7, 1);
+        // independent loads, issued together (one round trip)
         const int filled_k = ld_ctl(ctl, G_FILL + k % 3);
+        const int nk_next = ld_ctl(ctl, G_LIST + (k + 1) % 3);
         const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + k % 3);
         if (front_k > max_front) max_front = front_k;
         if (lw == 0 && tid == 0) {
@@ -319,7 +347,8 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
         if (filled_k == 0) break;
         total_filled += filled_k;
         K = k + 1;
-        nk = ld_ctl(ctl, G_LIST + (k + 1) % 3);
+        nk = nk_next;
+        GF_TACC(4);
     }
 
     // ---- finish -------------------------------------------------------------
@@ -368,15 +397,21 @@ struct BwdArgs {
     int ghost;
 };
 
+// Adjoint of one filled pixel x (shell k), one pass over its ball:
+//   u = (1/S) sum_j w_j v_j,  S = sum_j w_j,  log w_j = -a (g_perp . o_j)^2 - log|o_j|
+//   du/dg = (1/S) sum_j w_j ((v_j - u) dlog w_j/dg + dv_j/dg)
+//         = (1/S) [sum_j w_j v_j dlw_j - u sum_j w_j dlw_j + sum_j w_j dv_j]
+// so every sum is accumulated in the same pass as S and u; |o_j| does not
+// depend on g (the rotation preserves length).  A second pass scatters
+// ubar(x) w_j / S times the bilinear basis values into the support pixels.
 template <typename TS, int G>
 __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rinv, int T,
-                          long long gidx, int k, int l) {
+                          long long gidx, float2 gv, int k, int l) {
     const long long f = gidx / A.HW;
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
     const int W = A.W;
     const int32_t *S = A.shell + f * A.HW;
-    const float2 gv = reinterpret_cast<const float2 *>(A.guide)[gidx];
     const double gx = (double)gv.x, gy = (double)gv.y;
     const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
     double cs = 0.0, sn = 0.0, L = 1.0;
@@ -387,22 +422,34 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     }
     const int C = A.C;
     const TS *U = reinterpret_cast<const TS *>(A.img) + f * A.HW * C;
-    double q[kPerLaneMax];
-    unsigned rmask = 0;
+    // pass 1: geometry and readable set (kept for the other passes)
+    double fxs[kPerLaneMax], fys[kPerLaneMax], q[kPerLaneMax];
+    int base[kPerLaneMax];
+    unsigned rmask = 0, exmask = 0, eymask = 0;
     double qmin = INFINITY;
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
+        fxs[r] = fys[r] = 0.0;
         q[r] = INFINITY;
+        base[r] = 0;
         const int t = l + r * G;
         if (t < T) {
             const short2 nm = off[t];
             double ox, oy;
             rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
-            const Support s = support_of(X, Y, ox, oy);
+            const double fx0 = floor(ox), fy0 = floor(oy);
+            const bool ex = (ox == fx0), ey = (oy == fy0);
+            const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
+            const int x1 = x0 + (ex ? 0 : 1), y1 = y0 + (ey ? 0 : 1);
+            fxs[r] = ex ? 0.0 : ox - fx0;
+            fys[r] = ey ? 0.0 : oy - fy0;
+            exmask |= ex ? (1u << r) : 0u;
+            eymask |= ey ? (1u << r) : 0u;
             bool rd = false;
-            if (s.x0 >= 0 && s.y0 >= 0 && s.x1 < A.W && s.y1 < A.H) {
-                const int32_t a0 = S[s.y0 * W + s.x0], a1 = S[s.y0 * W + s.x1];
-                const int32_t a2 = S[s.y1 * W + s.x0], a3 = S[s.y1 * W + s.x1];
+            if (x0 >= 0 && y0 >= 0 && x1 < A.W && y1 < A.H) {
+                base[r] = y0 * W + x0;
+                const int32_t a0 = S[y0 * W + x0], a1 = S[y0 * W + x1];
+                const int32_t a2 = S[y1 * W + x0], a3 = S[y1 * W + x1];
                 rd = ((int)readable(a0, k) & (int)readable(a1, k) & (int)readable(a2, k) &
                       (int)readable(a3, k)) != 0;
             }
@@ -415,55 +462,22 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
         }
     }
     qmin = gmin<G>(qmin);
-    // weights, values and the value of x
+    // pass 2: weights, values, value derivatives, all sums
     double w[kPerLaneMax];
-    double v[kPerLaneMax][4];
-    double Ssum = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+    double Ssum = 0.0, Bx = 0.0, By = 0.0;
+    double Uc[4] = {0.0, 0.0, 0.0, 0.0}, Ax[4] = {0.0, 0.0, 0.0, 0.0}, Ay[4] = {0.0, 0.0, 0.0, 0.0};
+    double Dx[4] = {0.0, 0.0, 0.0, 0.0}, Dy[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
         w[r] = 0.0;
-        v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
         if (rmask & (1u << r)) {
             const int t = l + r * G;
             const short2 nm = off[t];
             double ox, oy;
             rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
-            const Support s = support_of(X, Y, ox, oy);
-            w[r] = exp(-(q[r] - qmin)) * rinv[t];
-            Ssum += w[r];
-            const double b00 = s.wx0 * s.wy0, b10 = s.wx1 * s.wy0, b01 = s.wx0 * s.wy1,
-                         b11 = s.wx1 * s.wy1;
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                if (ch < C) {
-                    v[r][ch] = b00 * load_px(U + (long long)(s.y0 * W + s.x0) * C + ch) +
-                               b10 * load_px(U + (long long)(s.y0 * W + s.x1) * C + ch) +
-                               b01 * load_px(U + (long long)(s.y1 * W + s.x0) * C + ch) +
-                               b11 * load_px(U + (long long)(s.y1 * W + s.x1) * C + ch);
-                    u[ch] += w[r] * v[r][ch];
-                }
-            }
-        }
-    }
-    Ssum = gsum<G>(Ssum);
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) u[ch] = gsum<G>(u[ch]) / Ssum;
-    double ub[4] = {0.0, 0.0, 0.0, 0.0};
-    float *GI = A.grad_img;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) ub[ch] = (double)GI[gidx * C + ch];
-    double dgx = 0.0, dgy = 0.0;
-#pragma unroll
-    for (int r = 0; r < kPerLaneMax; ++r) {
-        if (rmask & (1u << r)) {
-            const int t = l + r * G;
-            const short2 nm = off[t];
-            double ox, oy;
-            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
-            const Support s = support_of(X, Y, ox, oy);
-            const double lam = w[r] / Ssum;
+            const double wr = exp(-(q[r] - qmin)) * rinv[t];
+            w[r] = wr;
+            Ssum += wr;
             double dox_dgx = 0.0, dox_dgy = 0.0, doy_dgx = 0.0, doy_dgy = 0.0;
             if (rot) {  // o rotates with g: d(theta) = (c dgy - s dgx) / |g|
                 dox_dgx = sn * oy / L;
@@ -472,41 +486,72 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
                 doy_dgy = cs * ox / L;
             }
             const double tp = (-gy) * ox + gx * oy;
-            const double dt_dgx = oy + (-gy) * dox_dgx + gx * doy_dgx;
-            const double dt_dgy = -ox + (-gy) * dox_dgy + gx * doy_dgy;
-            const double r2 = ox * ox + oy * oy;
-            const double dlw_dgx = -2.0 * A.a * tp * dt_dgx - (ox * dox_dgx + oy * doy_dgx) / r2;
-            const double dlw_dgy = -2.0 * A.a * tp * dt_dgy - (ox * dox_dgy + oy * doy_dgy) / r2;
-            const bool ex = s.x1 == s.x0, ey = s.y1 == s.y0;
-            const long long i00 = f * A.HW + (long long)s.y0 * W + s.x0;
-            const long long i10 = f * A.HW + (long long)s.y0 * W + s.x1;
-            const long long i01 = f * A.HW + (long long)s.y1 * W + s.x0;
-            const long long i11 = f * A.HW + (long long)s.y1 * W + s.x1;
+            const double dlx = -2.0 * A.a * tp * (oy + (-gy) * dox_dgx + gx * doy_dgx);
+            const double dly = -2.0 * A.a * tp * (-ox + (-gy) * dox_dgy + gx * doy_dgy);
+            Bx += wr * dlx;
+            By += wr * dly;
+            const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
+            const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
+            const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W),
+                      i11 = i01 + (ex ? 0 : 1);
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
-                    const double u00 = load_px(U + (long long)(s.y0 * W + s.x0) * C + ch);
-                    const double u10 = load_px(U + (long long)(s.y0 * W + s.x1) * C + ch);
-                    const double u01 = load_px(U + (long long)(s.y1 * W + s.x0) * C + ch);
-                    const double u11 = load_px(U + (long long)(s.y1 * W + s.x1) * C + ch);
-                    const double vpx = ex ? 0.0 : s.wy0 * (u10 - u00) + s.wy1 * (u11 - u01);
-                    const double vpy = ey ? 0.0 : s.wx0 * (u01 - u00) + s.wx1 * (u11 - u10);
-                    const double dvx = vpx * dox_dgx + vpy * doy_dgx;
-                    const double dvy = vpx * dox_dgy + vpy * doy_dgy;
-                    dgx += ub[ch] * lam * ((v[r][ch] - u[ch]) * dlw_dgx + dvx);
-                    dgy += ub[ch] * lam * ((v[r][ch] - u[ch]) * dlw_dgy + dvy);
-                    // pass the adjoint to the bilinear support
-                    const double g = ub[ch] * lam;
-                    unsafeAtomicAdd(&GI[i00 * C + ch], (float)(g * s.wx0 * s.wy0));
-                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], (float)(g * s.wx1 * s.wy0));
-                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], (float)(g * s.wx0 * s.wy1));
-                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], (float)(g * s.wx1 * s.wy1));
+                    const double u00 = load_px(U + (long long)i00 * C + ch);
+                    const double u10 = load_px(U + (long long)i10 * C + ch);
+                    const double u01 = load_px(U + (long long)i01 * C + ch);
+                    const double u11 = load_px(U + (long long)i11 * C + ch);
+                    const double v = wx0 * wy0 * u00 + wx1 * wy0 * u10 + wx0 * wy1 * u01 +
+                                     wx1 * wy1 * u11;
+                    const double vpx = ex ? 0.0 : wy0 * (u10 - u00) + wy1 * (u11 - u01);
+                    const double vpy = ey ? 0.0 : wx0 * (u01 - u00) + wx1 * (u11 - u10);
+                    Uc[ch] += wr * v;
+                    Ax[ch] += wr * v * dlx;
+                    Ay[ch] += wr * v * dly;
+                    Dx[ch] += wr * (vpx * dox_dgx + vpy * doy_dgx);
+                    Dy[ch] += wr * (vpx * dox_dgy + vpy * doy_dgy);
                 }
             }
         }
     }
-    dgx = gsum<G>(dgx);
-    dgy = gsum<G>(dgy);
+    Ssum = gsum<G>(Ssum);
+    Bx = gsum<G>(Bx);
+    By = gsum<G>(By);
+    const double inv = 1.0 / Ssum;
+    float *GI = A.grad_img;
+    double ub[4] = {0.0, 0.0, 0.0, 0.0};
+    double dgx = 0.0, dgy = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        if (ch < C) {
+            ub[ch] = (double)GI[gidx * C + ch];
+            const double u = gsum<G>(Uc[ch]) * inv;
+            dgx += ub[ch] * (gsum<G>(Ax[ch]) - u * Bx + gsum<G>(Dx[ch])) * inv;
+            dgy += ub[ch] * (gsum<G>(Ay[ch]) - u * By + gsum<G>(Dy[ch])) * inv;
+        }
+    }
+    // pass 3: pass the adjoint to the bilinear supports
+    const long long fo = f * A.HW;
+#pragma unroll
+    for (int r = 0; r < kPerLaneMax; ++r) {
+        if (rmask & (1u << r)) {
+            const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
+            const double lam = w[r] * inv;
+            const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
+            const long long i00 = fo + base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W),
+                            i11 = i01 + (ex ? 0 : 1);
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ch < C) {
+                    const double g = ub[ch] * lam;
+                    unsafeAtomicAdd(&GI[i00 * C + ch], (float)(g * wx0 * wy0));
+                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], (float)(g * wx1 * wy0));
+                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], (float)(g * wx0 * wy1));
+                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], (float)(g * wx1 * wy1));
+                }
+            }
+        }
+    }
     if (l == 0) {
         A.grad_guide[gidx * 2 + 0] = (float)dgx;
         A.grad_guide[gidx * 2 + 1] = (float)dgy;
@@ -519,6 +564,8 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
     __shared__ int s_T;
+    __shared__ int s_item[kItemCap];
+    __shared__ float2 s_gd[kItemCap];
     const int tid = threadIdx.x;
     const int nblk = (int)gridDim.x;
     const int lw = logical_block();
@@ -539,9 +586,19 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
         const long long b0 = A.shell_off[k], b1 = A.shell_off[k + 1];
         const long long n = b1 - b0;
         const long long lo = b0 + n * lw / nblk, hi = b0 + n * (lw + 1) / nblk;
-        for (long long base = lo; base < hi; base += nG) {
-            const long long item = base + gi;
-            if (item < hi) bwd_pixel<TS, G>(A, s_off, s_rinv, T, (long long)A.order[item], k, l);
+        for (long long c0 = lo; c0 < hi; c0 += kItemCap) {  // items and guides via LDS
+            const int cn = (int)min((long long)kItemCap, hi - c0);
+            __syncthreads();
+            for (int i = tid; i < cn; i += kBlock) {
+                const int gidx = A.order[c0 + i];
+                s_item[i] = gidx;
+                s_gd[i] = reinterpret_cast<const float2 *>(A.guide)[gidx];
+            }
+            __syncthreads();
+            for (int base = 0; base < cn; base += nG) {
+                const int item = base + gi;
+                if (item < cn) bwd_pixel<TS, G>(A, s_off, s_rinv, T, s_item[item], s_gd[item], k, l);
+            }
         }
         grid_sync(A.ctl, (unsigned)nblk);
     }

@@ -99,19 +99,22 @@ gf_status validate(const gf_params *p, int B, int H, int W, int C, gf_dtype dt) 
     if (p->engine != GF_ENGINE_TILED && p->engine != GF_ENGINE_FRONT) return GF_EINVAL;
     if (p->group != 0 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
         return GF_EINVAL;
-    if (p->group == 8 && p->engine != GF_ENGINE_TILED) return GF_EINVAL;
     if (p->blocks_per_cu < 0 || p->blocks_per_cu > 8) return GF_EINVAL;
     if (p->tile_w < 0 || p->tile_h < 0 || p->tile_w > 256 || p->tile_h > 256) return GF_EINVAL;
     if (p->pass_shells < 0 || p->pass_shells > 32) return GF_EINVAL;
+    if (p->tile_threads != 0 && p->tile_threads != 256 && p->tile_threads != 512 &&
+        p->tile_threads != 1024)
+        return GF_EINVAL;
+    if (p->tile_threads != 0 && p->engine != GF_ENGINE_TILED) return GF_EINVAL;
     long long np = (long long)B * H * W;
     if (np * C >= (1ll << 31)) return GF_EUNSUPPORTED;  // int32 pixel indices in the lists
     return GF_OK;
 }
 
+// lanes per pixel: the smallest group with at most 4 offsets per lane
 int pick_group(const gf_params *p, int T) {
     if (p->group) return p->group;
-    if (p->engine == GF_ENGINE_TILED) return T <= 32 ? 8 : (T <= 64 ? 16 : (T <= 128 ? 32 : 64));
-    return T <= 32 ? 32 : 64;
+    return T <= 32 ? 8 : (T <= 64 ? 16 : (T <= 128 ? 32 : 64));
 }
 
 // tile geometry of the tiled engine
@@ -125,7 +128,7 @@ int rdep_of(double eps) { return (int)ceil(eps); }
 template <typename TS>
 bool tile_geometry(const gf_params *p, int C, size_t lds_limit, TileGeom &g) {
     const int rd = rdep_of(p->eps);
-    const size_t static_lds = 12 * 1024;  // staging buffer, offsets, counters
+    const size_t static_lds = kTileStaticLds;  // staging buffer, offsets, counters
     int S = p->pass_shells ? p->pass_shells : (rd <= 3 ? 4 : (rd <= 6 ? 3 : 2));
     for (;;) {
         const int Hh = S * rd;
@@ -221,24 +224,36 @@ gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long lo
 template <typename TS>
 gf_status run_front(const FillArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
+    if (G == 8) return launch_coop(fill_kernel<TS, 8>, &A, bpc, mb, 0, s);
     if (G == 16) return launch_coop(fill_kernel<TS, 16>, &A, bpc, mb, 0, s);
     if (G == 32) return launch_coop(fill_kernel<TS, 32>, &A, bpc, mb, 0, s);
     return launch_coop(fill_kernel<TS, 64>, &A, bpc, mb, 0, s);
 }
 
-template <typename TS>
-gf_status run_tiled(const TileArgs &A, int G, int bpc, size_t lds, hipStream_t s) {
+// threads per tile workgroup
+int tile_threads_of(const gf_params *p) { return p->tile_threads ? p->tile_threads : 1024; }
+
+template <typename TS, int NT>
+gf_status run_tiled_nt(const TileArgs &A, int G, int bpc, size_t lds, hipStream_t s) {
     const long long mb = 1ll << 30;
-    const int b = kTileBlock;
-    if (G == 8) return launch_coop(tile_kernel<TS, 8>, &A, bpc, mb, lds, s, b);
-    if (G == 16) return launch_coop(tile_kernel<TS, 16>, &A, bpc, mb, lds, s, b);
-    if (G == 32) return launch_coop(tile_kernel<TS, 32>, &A, bpc, mb, lds, s, b);
-    return launch_coop(tile_kernel<TS, 64>, &A, bpc, mb, lds, s, b);
+    if (bpc == 0) bpc = 8;  // as many workgroups per CU as the LDS and registers allow
+    if (G == 8) return launch_coop(tile_kernel<TS, 8, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 16) return launch_coop(tile_kernel<TS, 16, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 32) return launch_coop(tile_kernel<TS, 32, NT>, &A, bpc, mb, lds, s, NT);
+    return launch_coop(tile_kernel<TS, 64, NT>, &A, bpc, mb, lds, s, NT);
+}
+
+template <typename TS>
+gf_status run_tiled(const TileArgs &A, int G, int NT, int bpc, size_t lds, hipStream_t s) {
+    if (NT == 256) return run_tiled_nt<TS, 256>(A, G, bpc, lds, s);
+    if (NT == 512) return run_tiled_nt<TS, 512>(A, G, bpc, lds, s);
+    return run_tiled_nt<TS, 1024>(A, G, bpc, lds, s);
 }
 
 template <typename TS>
 gf_status run_bwd(const BwdArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
+    if (G == 8) return launch_coop(bwd_kernel<TS, 8>, &A, bpc, mb, 0, s);
     if (G == 16) return launch_coop(bwd_kernel<TS, 16>, &A, bpc, mb, 0, s);
     if (G == 32) return launch_coop(bwd_kernel<TS, 32>, &A, bpc, mb, 0, s);
     return launch_coop(bwd_kernel<TS, 64>, &A, bpc, mb, 0, s);
@@ -421,8 +436,9 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     A.eps = p->eps;
     A.a = a;
     A.c = p->c;
-    if (dt == GF_F32) return run_tiled<float>(A, G, p->blocks_per_cu, geom.lds, s);
-    return run_tiled<__half>(A, G, p->blocks_per_cu, geom.lds, s);
+    const int NT = tile_threads_of(p);
+    if (dt == GF_F32) return run_tiled<float>(A, G, NT, p->blocks_per_cu, geom.lds, s);
+    return run_tiled<__half>(A, G, NT, p->blocks_per_cu, geom.lds, s);
 }
 
 gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,

@@ -44,50 +44,58 @@ struct TileArgs {
     double eps, a, c;
 };
 
-// Optional timing hooks (compiled in only with -DGF_TRACE, for profiling
-// builds): per-workgroup accumulators of wall-clock ticks and counts.
-#ifdef GF_TRACE
-constexpr int kTraceSlots = 16;
-__device__ long long gf_trace[4096 * kTraceSlots];
-#define GF_T0() long long gf_t_last = wall_clock64()
-#define GF_TACC(slot)                                                                   \
-    do {                                                                                \
-        if (threadIdx.x == 0) {                                                         \
-            const long long gf_t_now = wall_clock64();                                  \
-            gf_trace[blockIdx.x * kTraceSlots + (slot)] += gf_t_now - gf_t_last;        \
-            gf_t_last = gf_t_now;                                                       \
-        }                                                                               \
-    } while (0)
-#define GF_TCNT(slot, v)                                                                \
-    do {                                                                                \
-        if (threadIdx.x == 0) gf_trace[blockIdx.x * kTraceSlots + (slot)] += (v);       \
-    } while (0)
-#else
-#define GF_T0()
-#define GF_TACC(slot)
-#define GF_TCNT(slot, v)
-#endif
 
-constexpr int kTileBlock = 1024;  // one 16-wave workgroup per CU
-constexpr int kWinPerThread = 8;  // window pixels staged per thread per round trip
-constexpr int kMaxWindow = kTileBlock * kWinPerThread;
+constexpr int kWinPerThread = 4;     // window pixels staged per thread per round trip
+constexpr int kMaxWindow = 8192;     // window pixels (uint16 local lists)
+constexpr int kTileStageCap = 512;   // LDS staging of next-pass tiles per workgroup
+constexpr int kTileStaticLds = 8192; // bytes of static LDS the tile kernel may use
+
+constexpr int kCopyChunk = 16384;    // pixels per job of the deferred out-of-place copy
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Out-of-place form: every pixel that is not a hole pixel (label != 1) takes
+// its input colour; hole pixels are written by the fill (or, never filled, at
+// the end).  Pixels [p0, p1), four per thread per step, loads before stores.
+template <typename TS, int NT>
+__device__ void copy_known(const TS *in, TS *out, const uint8_t *label, int C, long long p0,
+                           long long p1) {
+    for (long long q = p0 + 4 * (long long)threadIdx.x; q < p1; q += 4 * (long long)NT) {
+        uint8_t lab[4];
+        TS v[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lab[j] = q + j < p1 ? label[q + j] : (uint8_t)1;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                if (ch < C && q + j < p1) v[j][ch] = in[(q + j) * C + ch];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (lab[j] != 1) {
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (ch < C) out[(q + j) * C + ch] = v[j][ch];
+            }
+    }
+}
 
 // LDS of one window: states (int32), colours (storage type), guide (float2),
 // two local front lists (uint16)
 template <typename TS> __host__ __device__ inline size_t tile_lds_bytes(int WN, int C) {
-    return align16((size_t)WN * 4) + align16((size_t)WN * C * sizeof(TS)) +
+    return align16((size_t)WN * 4) + align16((size_t)WN * padded_channels(C) * sizeof(TS)) +
            align16((size_t)WN * 8) + (size_t)WN * 4;
 }
 
-template <typename TS, int G>
-__global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
+// NT threads per workgroup: 1024 (one large window per CU) or 256 (several
+// small windows share a CU)
+template <typename TS, int G, int NT>
+__global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
     __shared__ int s_T;
-    __shared__ int s_stage[kStageCap];
+    __shared__ int s_stage[kTileStageCap];
     __shared__ int s_stage_n;
     __shared__ int s_base;
     __shared__ int s_fn[2];       // local front lengths
@@ -96,18 +104,20 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     __shared__ int s_pass_fill, s_pass_kmax, s_hole_n, s_err_n;
     __shared__ int s_front_in[32];  // interior active pixels per local shell
     __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
+    __shared__ int s_job;           // deferred copy: the chunk taken
 
     const int tid = threadIdx.x;
     const int nblk = (int)gridDim.x;
     const int lw = logical_block();
     const int xcd = (int)(blockIdx.x % kXcd);
     const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
+    const int CP = padded_channels(C);  // channels per window pixel
     int32_t *st = reinterpret_cast<int32_t *>(smem);
     TS *col = reinterpret_cast<TS *>(smem + align16((size_t)WN * 4));
     float2 *gd = reinterpret_cast<float2 *>(smem + align16((size_t)WN * 4) +
-                                            align16((size_t)WN * C * sizeof(TS)));
+                                            align16((size_t)WN * CP * sizeof(TS)));
     uint16_t *fl = reinterpret_cast<uint16_t *>(smem + align16((size_t)WN * 4) +
-                                                align16((size_t)WN * C * sizeof(TS)) +
+                                                align16((size_t)WN * CP * sizeof(TS)) +
                                                 align16((size_t)WN * 8));
     int32_t *ctl = A.ctl;
     build_offsets(A.eps, s_off, s_rinv, &s_T);
@@ -121,30 +131,41 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     const int T = s_T;
     const int Rb = (int)floor(A.eps);
     const int tpf = A.tiles_x * A.tiles_y;  // tiles per frame
-    Stage stage{s_stage, &s_stage_n};
+    Stage stage{s_stage, &s_stage_n, kTileStageCap};
     GF_T0();
 
-    // ---- phase A: copy, shell codes, per-tile hole counts, pass-0 tiles ----
-    if (!A.inplace) {
-        const size_t esz = sizeof(TS) * (size_t)C;
-        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
-        copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
-                   (size_t)lo * esz, (size_t)hi * esz);
-    }
+    // The out-of-place copy of known pixels is deferred: windows read original
+    // colours from the input, and the copy runs in chunks taken from a global
+    // counter by workgroups that have no tile in a pass, the rest at the end.
+    const long long ncopy = A.inplace ? 0 : (A.NP + kCopyChunk - 1) / kCopyChunk;
+    auto copy_jobs = [&](long long max_jobs) {
+        for (long long j = 0; j < max_jobs; ++j) {
+            __syncthreads();
+            if (tid == 0) s_job = atomicAdd(&ctl[G_COPY], 1);
+            __syncthreads();
+            const long long c = s_job;
+            if (c >= ncopy) break;  // uniform across the workgroup
+            const long long p0 = c * kCopyChunk, p1 = min(A.NP, p0 + kCopyChunk);
+            copy_known<TS, NT>(reinterpret_cast<const TS *>(A.in), reinterpret_cast<TS *>(A.out),
+                               A.label, C, p0, p1);
+        }
+    };
+
+    // ---- phase A: shell codes, per-tile hole counts, pass-0 tiles ------------
     {
         const int tpx = A.TW * A.TH;
-        int nb = (kWinPerThread * kTileBlock) / tpx;  // tiles per batch: <= 8 labels per thread
+        int nb = (kWinPerThread * NT) / tpx;  // tiles per batch: <= kWinPerThread labels per thread
         nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
         for (int b0 = 0; lw + b0 * nblk < A.ntiles; b0 += nb) {
             if (tid < 16) s_tcnt[tid] = 0;
             __syncthreads();
-            for (int sb = 0; sb < nb * tpx; sb += kWinPerThread * kTileBlock) {
+            for (int sb = 0; sb < nb * tpx; sb += kWinPerThread * NT) {
             uint8_t lab[kWinPerThread];
             long long pix[kWinPerThread];
             int tj[kWinPerThread];
 #pragma unroll
             for (int r = 0; r < kWinPerThread; ++r) {
-                const int slot = sb + tid + r * kTileBlock;
+                const int slot = sb + tid + r * NT;
                 tj[r] = -1;
                 pix[r] = 0;
                 lab[r] = 0;
@@ -204,7 +225,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     const int total_hole = sum_x(ctl, XF_HOLE);
     long long total_filled = 0;
     int max_front = 0;  // kept by thread 0 of logical workgroup 0
-    const int nG = kTileBlock / G;
+    const int nG = NT / G;
     const int gi = tid / G, l = tid & (G - 1);
     const int wave_base = tid & ~63;
     for (int p = 0; total_filled < total_hole; ++p) {
@@ -248,16 +269,19 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
             const int ox0 = tx * A.TW - A.Hh, oy0 = ty * A.TH - A.Hh;
             const int32_t *S = A.shell + (long long)f * A.HW;
             const TS *U = reinterpret_cast<const TS *>(A.out) + (long long)f * A.HW * C;
+            const TS *Uin = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
             const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
             // 1. stage the window in two round trips: states (readable before the
             //    pass / bystander / hole; pixels filled by neighbours during this pass
             //    count as hole), then colours of readable and guides of hole pixels
-            for (int base = 0; base < WN; base += kWinPerThread * kTileBlock) {
+            for (int base = 0; base < WN; base += kWinPerThread * NT) {
                 int32_t code[kWinPerThread];
+                bool orig[kWinPerThread];  // known from the start: colour from the input
 #pragma unroll
                 for (int r = 0; r < kWinPerThread; ++r) {
-                    const int i = base + tid + r * kTileBlock;
+                    const int i = base + tid + r * NT;
                     code[r] = S_BYSTANDER;
+                    orig[r] = false;
                     if (i < WN) {
                         const int wy = i / WW, wx = i - wy * WW;
                         const int x = ox0 + wx, y = oy0 + wy;
@@ -265,20 +289,41 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                             const int32_t s = S[y * W + x];
                             code[r] = (s == -1 || (s >= 0 && s < k0)) ? S_READABLE
                                       : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
+                            orig[r] = s == -1;
+                        }
+                    }
+                }
+                // every load of the second round trip is issued before the first
+                // LDS store that needs one
+                TS cv[kWinPerThread][4];
+                float2 gv[kWinPerThread];
+#pragma unroll
+                for (int r = 0; r < kWinPerThread; ++r) {
+                    const int i = base + tid + r * NT;
+                    if (i < WN) {
+                        const int wy = i / WW, wx = i - wy * WW;
+                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
+                        if (code[r] == S_READABLE) {
+                            const TS *src = orig[r] ? Uin : U;
+#pragma unroll
+                            for (int ch = 0; ch < 4; ++ch)
+                                if (ch < C) cv[r][ch] = src[q * C + ch];
+                        } else if (code[r] == S_HOLE) {
+                            gv[r] = Gd[q];
                         }
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < kWinPerThread; ++r) {
-                    const int i = base + tid + r * kTileBlock;
+                    const int i = base + tid + r * NT;
                     if (i < WN) {
                         st[i] = code[r];
-                        const int wy = i / WW, wx = i - wy * WW;
-                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
                         if (code[r] == S_READABLE) {
-                            for (int ch = 0; ch < C; ++ch) col[i * C + ch] = U[q * C + ch];
+#pragma unroll
+                            for (int ch = 0; ch < 4; ++ch)
+                                if (ch < C) col[i * CP + ch] = cv[r][ch];
                         } else if (code[r] == S_HOLE) {
-                            gd[i] = Gd[q];
+                            gd[i] = gv[r];
                         }
                     }
                 }
@@ -293,7 +338,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
             GF_TCNT(6, 1);
             // 2. local shells
             if (A.local_track) {
-                for (int i = tid; i < WN; i += kTileBlock) {
+                for (int i = tid; i < WN; i += NT) {
                     if (st[i] != S_HOLE) continue;
                     const int wy = i / WW, wx = i - wy * WW;
                     bool act = false;
@@ -306,7 +351,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                     if (act) st[i] = S_FRONT;
                 }
                 __syncthreads();
-                for (int base = 0; base < WN; base += kTileBlock) {  // uniform trip count
+                for (int base = 0; base < WN; base += NT) {  // uniform trip count
                     const int i = base + tid;
                     const bool want = i < WN && st[i] == S_FRONT;
                     const int slot = wave_append(want, &s_fn[0]);
@@ -315,7 +360,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                 __syncthreads();
             }
             GF_TACC(2);
-            LdsView<TS> view{st, col, WW, A.WH, C};
+            LdsView<TS> view{st, col, WW, A.WH, C, CP};
             int cur = 0;
             for (int j = 0; j < Sp; ++j) {
                 // fill one window pixel with a group; returns ready, sets the counters
@@ -329,7 +374,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                     if (l == 0) {
                         interior = X >= A.Hh && X < A.Hh + A.TW && Y >= A.Hh && Y < A.Hh + A.TH;
                         if (ok) {
-                            for (int ch = 0; ch < C; ++ch) col[wi * C + ch] = to_storage<TS>(val[ch]);
+                            for (int ch = 0; ch < C; ++ch) col[wi * CP + ch] = to_storage<TS>(val[ch]);
                             st[wi] = j;
                             filled_here = true;
                         }
@@ -370,7 +415,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                         wave_count(interior, &s_front_in[j & 31]);
                     }
                 } else {
-                    for (int base = 0; base < WN; base += kTileBlock) {
+                    for (int base = 0; base < WN; base += NT) {
                         const int i = base + tid;
                         bool act = false;
                         if (i < WN && st[i] == S_HOLE) {
@@ -418,14 +463,14 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
                 const int tw = min(A.TW, W - tx * A.TW), th = min(A.TH, H - ty * A.TH);
                 TS *O = reinterpret_cast<TS *>(A.out) + (long long)f * A.HW * C;
                 int32_t *Sw = A.shell + (long long)f * A.HW;
-                for (int i = tid; i < tw * th; i += kTileBlock) {
+                for (int i = tid; i < tw * th; i += NT) {
                     const int ly = i / tw, lx = i - ly * tw;
                     const int wi = (ly + A.Hh) * WW + (lx + A.Hh);
                     const int v = st[wi];
                     const int y = ty * A.TH + ly, x = tx * A.TW + lx;
                     if (v >= 0) {
                         Sw[y * W + x] = k0 + v;
-                        for (int ch = 0; ch < C; ++ch) O[(long long)(y * W + x) * C + ch] = col[wi * C + ch];
+                        for (int ch = 0; ch < C; ++ch) O[(long long)(y * W + x) * C + ch] = col[wi * CP + ch];
                         ++nf;
                         km = max(km, k0 + v + 1);
                     } else if (v == S_HOLE || v == S_FRONT) {
@@ -465,6 +510,7 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
             }
             GF_TACC(4);
         }
+        if (lw >= n_tiles_pass && ncopy) copy_jobs(2);  // no tile in this pass
         stage_flush(stage, nxt_act, nxt_cnt, &s_base);
         if (tid == 0 && s_pass_fill) {
             atomicAdd(&ctl[xw(xcd, XF_PFILL + p % 3)], s_pass_fill);
@@ -487,21 +533,29 @@ __global__ __launch_bounds__(kTileBlock) void tile_kernel(TileArgs A) {
     }
 
     // ---- finish ---------------------------------------------------------------
-    if (total_filled < total_hole) {  // leftovers never became ready: shell -3
+    if (ncopy) copy_jobs(ncopy);  // the rest of the deferred copy
+    if (total_filled < total_hole) {  // leftovers never became ready: shell -3, input colour
         for (int t = lw; t < A.ntiles; t += nblk) {
             if (A.t_rem[t] == 0) continue;
             const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
             const int tw = min(A.TW, W - tx * A.TW), th = min(A.TH, H - ty * A.TH);
             int32_t *Sw = A.shell + (long long)f * A.HW;
-            for (int i = tid; i < tw * th; i += kTileBlock) {
+            const TS *Ui = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
+            TS *Uo = reinterpret_cast<TS *>(A.out) + (long long)f * A.HW * C;
+            for (int i = tid; i < tw * th; i += NT) {
                 const int y = ty * A.TH + i / tw, x = tx * A.TW + i % tw;
-                if (Sw[y * W + x] == S_HOLE) Sw[y * W + x] = S_UNFILLED;
+                if (Sw[y * W + x] == S_HOLE) {
+                    Sw[y * W + x] = S_UNFILLED;
+                    if (!A.inplace)
+                        for (int ch = 0; ch < C; ++ch)
+                            Uo[(long long)(y * W + x) * C + ch] = Ui[(long long)(y * W + x) * C + ch];
+                }
             }
         }
     }
     for (int f = lw; f < A.B; f += nblk) {  // per-frame statistics, one workgroup per frame
         int kf = 0, ff = 0, hf = 0;
-        for (int i = tid; i < tpf; i += kTileBlock) {
+        for (int i = tid; i < tpf; i += NT) {
             const int t = f * tpf + i;
             kf = max(kf, A.t_kmax[t]);
             ff += A.t_fill[t];

@@ -78,13 +78,20 @@ def _call(lib, params, B=1, H=8, W=8, C=3, dt=0, ptr=1 << 20, ws_bytes=1 << 20, 
     ("eps", 0.0), ("eps", 0.5), ("eps", 9.5), ("eps", float("nan")), ("mu", 0.0),
     ("mu", -1.0), ("mu", float("inf")), ("c", float("nan")), ("max_shells", -1),
     ("group", 4), ("blocks_per_cu", 9), ("blocks_per_cu", -1), ("engine", 2), ("engine", -1),
-    ("pass_shells", 33), ("pass_shells", -1), ("tile_w", 300), ("tile_h", -2)])
+    ("pass_shells", 33), ("pass_shells", -1), ("tile_w", 300), ("tile_h", -2),
+    ("tile_threads", 128), ("tile_threads", 768), ("tile_threads", -256)])
 def test_bad_parameters_are_rejected(lib, field, value):
     import paper_1611_05319_amd as gf
 
     p = gf.Params()
     setattr(p, field, value)
     assert _call(lib, p.c_struct()) == -1
+
+
+def test_tile_threads_only_with_the_tiled_engine(lib):
+    import paper_1611_05319_amd as gf
+
+    assert _call(lib, gf.Params(engine=gf.ENGINE_FRONT, tile_threads=256).c_struct()) == -1
 
 
 @pytest.mark.parametrize("shape", [(0, 8, 8, 3), (1, 0, 8, 3), (1, 8, 0, 3), (1, 8, 8, 0),
@@ -108,8 +115,10 @@ def test_tile_halo_must_fit_the_neighbour_tiles(lib):
     assert lib.gf_tile_geometry(1080, 1920, 3, 0, ctypes.byref(q), out) == 0
     tw, th, S, halo, lds, G = list(out)
     assert halo == S * 3 and halo <= tw and halo <= th and G in (8, 16, 32, 64)
-    f = gf.Params(engine=gf.ENGINE_FRONT, group=8).c_struct()  # 8 lanes: tiled engine only
-    assert _call(lib, f) == -1
+    # 8 lanes hold at most 32 ball offsets: eps = 5 (80 offsets) needs a wider group
+    for engine in (gf.ENGINE_TILED, gf.ENGINE_FRONT):
+        f = gf.Params(engine=engine, group=8, eps=5.0).c_struct()
+        assert _call(lib, f) == -3
     q5 = gf.Params(eps=5.0, mu=100.0).c_struct()
     assert lib.gf_tile_geometry(2160, 3840, 3, 0, ctypes.byref(q5), out) == 0
     assert out[3] == out[2] * 5 and out[3] <= out[0]

@@ -27,7 +27,10 @@ def _device():
     gf.load()
 
 
-ENGINES = [0, 1]  # tiled, global front
+# launch variants: the tiled engine (1024- and 256-thread workgroups) and the
+# global-front engine
+LAUNCH = {"tiled": {}, "tiled256": {"tile_threads": 256}, "front": {"engine": 1}}
+ENGINES = list(LAUNCH)
 
 
 def _check(img, lab, g, eps=3.0, mu=50.0, c=-1.0, ghost=True, tracking=True, ref=None, **kw):
@@ -50,7 +53,7 @@ def test_config1_tracked_and_untracked():
             for ghost in (True, False):
                 banner(f"c1 engine={engine} tracking={tracking} ghost={ghost}")
                 _check(w.image[0], w.label[0], w.guide[0], ghost=ghost, tracking=tracking,
-                       engine=engine)
+                       **LAUNCH[engine])
 
 
 CASES = [
@@ -83,7 +86,7 @@ def test_random_problems(case, tracking, engine):
     if c >= 0:
         assert ref.n_ties == 0, "confidence within the tie band of the threshold"
     _check(img, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, tracking=tracking, ref=ref,
-           engine=engine)
+           **LAUNCH[engine])
 
 
 def test_lattice_line_angles():
@@ -99,7 +102,7 @@ def test_lattice_line_angles():
     for engine in ENGINES:
         for tracking in (True, False):
             banner(f"lattice-line angles tracking={tracking} engine={engine}")
-            _check(img, lab, g, tracking=tracking, engine=engine, ref=ref)
+            _check(img, lab, g, tracking=tracking, **LAUNCH[engine], ref=ref)
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -111,12 +114,12 @@ def test_edge_cases(engine):
     # no hole at all
     banner("edge: no hole")
     lab = np.zeros((40, 50), np.uint8)
-    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
+    ref, u, s, st, _ = _check(img, lab, g, **LAUNCH[engine])
     assert st["K"] == 0 and st["hole"] == 0
     # everything is hole: nothing readable, nothing filled
     banner("edge: all hole")
     lab = np.ones((40, 50), np.uint8)
-    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
+    ref, u, s, st, _ = _check(img, lab, g, **LAUNCH[engine])
     assert (s == -3).all() and st["filled"] == 0
     # hole surrounded by bystanders (stall), and a hole on the image border
     banner("edge: stall")
@@ -124,7 +127,7 @@ def test_edge_cases(engine):
     lab[10:30, 10:30] = 2
     lab[15:25, 15:25] = 1
     lab[0:3, 40:50] = 1
-    ref, u, s, st, _ = _check(img, lab, g, engine=engine)
+    ref, u, s, st, _ = _check(img, lab, g, **LAUNCH[engine])
     assert (s[15:25, 15:25] == -3).all() and st["unfilled"] == 100
     # label values outside {0, 1, 2} are counted and act as bystanders
     banner("edge: bad labels")
@@ -134,7 +137,7 @@ def test_edge_cases(engine):
     ref_lab = lab.copy()
     ref_lab[20, 20] = 2
     ref = oracle.fill(img, ref_lab, g)
-    u, s, st, _ = gpu_fill(img, lab, g, engine=engine)
+    u, s, st, _ = gpu_fill(img, lab, g, **LAUNCH[engine])
     np.testing.assert_array_equal(s, ref.shell)
     assert st["label_errors"] == 1
 
@@ -159,7 +162,12 @@ FORMS = [
     {"tile_w": 40, "tile_h": 40, "pass_shells": 8}, {"tile_w": 24, "tile_h": 24, "pass_shells": 6},
     {"tile_w": 64, "tile_h": 16, "pass_shells": 5}, {"tile_w": 20, "tile_h": 36, "pass_shells": 3},
     {"tile_w": 24, "tile_h": 24, "pass_shells": 8, "tracking": False},
-    {"tile_w": 100, "tile_h": 120, "pass_shells": 2}, {},
+    {"tile_w": 100, "tile_h": 120, "pass_shells": 2},
+    {"tile_threads": 256}, {"tile_threads": 512}, {"tile_threads": 512, "pass_shells": 2},
+    {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "pass_shells": 4},
+    {"tile_threads": 256, "tile_w": 24, "tile_h": 12, "pass_shells": 2, "tracking": False},
+    {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "group": 16},
+    {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "blocks_per_cu": 2}, {},
 ]
 
 
@@ -183,7 +191,7 @@ def test_forms_agree_exactly():
         banner(f"form {kw}")
         u1, s1, st1, _ = gpu_fill(img, lab, g, **kw)
         np.testing.assert_array_equal(s1, s0)
-        G = kw.get("group") or (32 if kw.get("engine") == 1 else 8)
+        G = kw.get("group") or 8
         if G != 8:  # another reduction tree: the last FP64 bits may differ
             assert np.abs(u1 - u0).max() <= 2.0 ** -23
         else:
@@ -196,9 +204,9 @@ def test_forms_agree_exactly():
     bl = np.stack([f[1] for f in frames])
     bg = np.stack([f[2] for f in frames])
     for engine in ENGINES:
-        ub, sb, stb, _ = gpu_fill(bi, bl, bg, engine=engine)
+        ub, sb, stb, _ = gpu_fill(bi, bl, bg, **LAUNCH[engine])
         for i, (fi, fl, fg) in enumerate(frames):
-            ui, si, sti, _ = gpu_fill(fi, fl, fg, engine=engine)
+            ui, si, sti, _ = gpu_fill(fi, fl, fg, **LAUNCH[engine])
             np.testing.assert_array_equal(sb[i], si)
             np.testing.assert_array_equal(ub[i], ui)
             assert stb["frame_K"][i] == sti["K"] and stb["frame_filled"][i] == sti["filled"]
@@ -216,9 +224,9 @@ def test_front_sizes_match_active_boundary():
         for tracking in (True, False):
             # the tiled engine recounts only the tiles it visits: exact when no
             # pixel waits, which the lattice ball guarantees
-            for engine in ([1, 0] if not ghost else [1]):
+            for engine in (["front", "tiled", "tiled256"] if not ghost else ["front"]):
                 u, s, st, r = gpu_fill(img, lab, g, ghost=ghost, tracking=tracking,
-                                       engine=engine, record_fronts=True)
+                                       **LAUNCH[engine], record_fronts=True)
                 hist = r.front_hist.cpu().numpy()
                 np.testing.assert_array_equal(hist[:K], ref.front_hist[0, :K])
                 assert st["max_front"] == ref.max_front
@@ -229,14 +237,14 @@ def test_max_shells_resume(engine):
     banner("max_shells resume")
     rng = np.random.default_rng(9)
     img, lab, g = syn.random_tiny(rng, 100, 120, C=3, p_hole=0.5, p_bystander=0.05)
-    u_full, s_full, st_full, _ = gpu_fill(img, lab, g, engine=engine)
+    u_full, s_full, st_full, _ = gpu_fill(img, lab, g, **LAUNCH[engine])
     assert st_full["K"] >= 4
-    m = 3 if engine else 5  # 5 is not a multiple of the tiled engine's shells per pass
-    u1, s1, st1, _ = gpu_fill(img, lab, g, max_shells=m, engine=engine)
+    m = 3 if engine == "front" else 5  # 5 is not a multiple of the tiled engine's shells per pass
+    u1, s1, st1, _ = gpu_fill(img, lab, g, max_shells=m, **LAUNCH[engine])
     assert st1["K"] == m
     lab2 = lab.copy()
     lab2[s1 >= 0] = 0
-    u2, s2, _, _ = gpu_fill(u1.astype(np.float32), lab2, g, engine=engine)
+    u2, s2, _, _ = gpu_fill(u1.astype(np.float32), lab2, g, **LAUNCH[engine])
     s = np.where(s2 >= 0, s2 + m, s1)
     s = np.where((lab == 1) & (s1 >= 0), s1, s)
     np.testing.assert_array_equal(s, s_full)
@@ -252,7 +260,7 @@ def test_fp16_storage(engine):
     img, lab, g = syn.random_tiny(rng, 150, 170, C=3, p_hole=0.4, p_bystander=0.05)
     img16 = img.astype(np.float16)
     ref = oracle.fill(img16.astype(np.float64), lab, g, storage="f16")
-    u, s, st, _ = gpu_fill(img16.astype(np.float32), lab, g, dtype=torch.float16, engine=engine)
+    u, s, st, _ = gpu_fill(img16.astype(np.float32), lab, g, dtype=torch.float16, **LAUNCH[engine])
     np.testing.assert_array_equal(s, ref.shell)
     filled = s >= 0
     ulps = f16_ulps(u[filled], ref.u[filled])
@@ -267,7 +275,7 @@ def test_config2_full_size():
     for engine in ENGINES:
         for tracking in (True, False):
             banner(f"c2 1920x1080 tracking={tracking} engine={engine}")
-            ref, u, s, st, worst = _check(img, lab, g, tracking=tracking, engine=engine, ref=ref)
+            ref, u, s, st, worst = _check(img, lab, g, tracking=tracking, **LAUNCH[engine], ref=ref)
             banner(f"c2 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
 
 
@@ -277,7 +285,7 @@ def test_config3_full_size():
     for engine in ENGINES:
         banner(f"c3 3840x2160 eps=5 mu=100 engine={engine}")
         ref, u, s, st, worst = _check(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0,
-                                      ref=ref, engine=engine)
+                                      ref=ref, **LAUNCH[engine])
         banner(f"c3 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
         assert st["K"] > 50
 
@@ -297,3 +305,22 @@ def test_config4_batched_sampled():
         ulps = f16_ulps(u[f][filled], ref.u[filled])
         assert ulps.max() <= 1.0
         assert st["frame_K"][f] == ref.K and st["frame_filled"][f] == ref.n_filled
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_smart_order_threshold_on_a_straight_edge(engine):
+    # the ready test of eqn:ready taken just below and just above the closed-form
+    # confidence of a first-row pixel (oracle pin of the same name)
+    from test_oracle_pins import _half_plane_confidence
+
+    banner(f"smart-order threshold engine={engine}")
+    H, W, eps, mu = 10, 23, 3.0, 1.0
+    C0 = _half_plane_confidence(eps, mu, lambda n, m: n >= 1)
+    img = np.random.default_rng(5).uniform(0, 1, size=(H, W, 3)).astype(np.float32)
+    lab = np.zeros((H, W), dtype=np.uint8)
+    lab[4:] = 1
+    g = np.zeros((H, W, 2), dtype=np.float32)
+    g[..., 0] = 1.0
+    for c in (C0 * (1 - 1e-9), C0 * (1 + 1e-9)):
+        ref, u, s, st, _ = _check(img, lab, g, eps=eps, mu=mu, c=c, **LAUNCH[engine])
+        assert (s[4, W // 2] == 0) == (c < C0)

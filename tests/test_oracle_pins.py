@@ -338,3 +338,53 @@ def test_paper_connect_lines_claims():
         slope = (u[-1] - u[-61]) / 60.0
         meas = math.degrees(math.atan2(1.0, -slope))
         assert abs(meas - case["transport_deg"]) <= case["tol_deg"], (case, meas)
+
+
+def _half_plane_confidence(eps, mu, readable):
+    """Sec. 3.4 eqn:confidence for a ball whose offsets stay on the lattice:
+    the weights of eqn:weight over the readable offsets divided by those over
+    the whole ball (Rotated by a multiple of 90 degrees, o is an integer
+    offset; |g| = 1 and g_perp . o = n for these guides)."""
+    R = int(math.floor(eps))
+    a = mu * mu / (2.0 * eps * eps)
+    num = den = 0.0
+    for m in range(-R, R + 1):
+        for n in range(-R, R + 1):
+            r2 = n * n + m * m
+            if r2 == 0 or r2 > eps * eps:
+                continue
+            w = math.exp(-a * n * n) / math.sqrt(r2)
+            den += w
+            if readable(n, m):
+                num += w
+    return num / den
+
+
+@pytest.mark.parametrize("guide,readable", [
+    # g = (1, 0) along the edge: R(n, m) = (m, -n); the ghost point lies n rows up
+    ((1.0, 0.0), lambda n, m: n >= 1),
+    # g = (0, 1) across the edge: R(n, m) = (n, m); the ghost point lies -m rows up
+    ((0.0, 1.0), lambda n, m: m <= -1),
+])
+@pytest.mark.parametrize("eps,mu", [(3.0, 1.0), (3.0, 2.0), (2.0, 1.5)])
+def test_smart_order_threshold_on_a_straight_edge(guide, readable, eps, mu):
+    # rows 0..3 known, rows 4.. hole: a first-row pixel away from the side
+    # borders has confidence C0 from the closed form above; it is ready in
+    # shell 0 exactly when C0 > c (eqn:ready)
+    H, W = 10, 23
+    C0 = _half_plane_confidence(eps, mu, readable)
+    assert 0.0 < C0 < 1.0
+    img = np.random.default_rng(5).uniform(0, 1, size=(H, W, 1))
+    lab = np.zeros((H, W), dtype=np.uint8)
+    lab[4:] = 1
+    g = np.zeros((H, W, 2))
+    g[..., 0], g[..., 1] = guide
+    mid = W // 2
+    below = oracle.fill(img, lab, g, eps=eps, mu=mu, c=C0 * (1 - 1e-9))
+    above = oracle.fill(img, lab, g, eps=eps, mu=mu, c=C0 * (1 + 1e-9))
+    assert below.shell[4, mid] == 0
+    assert above.shell[4, mid] != 0
+    # every first-row pixel whose ball stays inside the image behaves the same
+    inner = slice(int(math.ceil(eps)), W - int(math.ceil(eps)))
+    assert (below.shell[4, inner] == 0).all()
+    assert (above.shell[4, inner] != 0).all()
