@@ -84,6 +84,8 @@ enum {
                                 tiled engine counts as for front_hist below) */
     GF_STAT_LABEL_ERR = 4,   /* label values outside {0, 1, 2} */
     GF_STAT_ORDER_TRUNC = 5, /* 1 if shell_offsets was too short for K + 1 entries */
+    GF_STAT_SYNC_TIMEOUT = 6,/* 1 if a grid barrier gave up waiting (never expected; the
+                                results are then invalid) */
     GF_STAT_FRAME0 = 8,      /* then per frame f at 8 + 4 f: K_f, filled_f, hole_f, 0 */
     GF_STAT_PER_FRAME = 4
 };

@@ -37,14 +37,18 @@ enum : int {
     G_GEN = 256,    // barrier generation
     G_TOP = 288,    // barrier arrivals of XCD groups
     G_LIST = 320,   // [3] front-list lengths (global engine), ring by shell
-    G_FILL = 352,   // [3] pixels filled in the shell (global engine)
     G_ACTIVE = 384, // [3] active pixels (global engine, untracked)
     G_HOLE = 416,
     G_ERR = 448,
     G_ORDER = 480,  // entries written to order_out
     G_FRONT = 512,  // [2][32] front sizes per local shell, ring by pass (tiled engine)
-    G_COPY = 640,   // next chunk of the deferred out-of-place copy (tiled engine)
+    G_FILLED = 608, // pixels filled so far (global engine)
+    G_TOP2 = 640,   // 64-bit: counting barrier, arrivals of XCD groups and their sums
+    G_GEN2 = 672,   // 64-bit: counting barrier, generation and the published sums
+    G_TIMEOUT = 704,// set when a barrier wait exceeded its spin limit
 };
+constexpr int XF_SUM = 10;  // 64-bit per-XCD word of the counting barrier (even index)
+constexpr unsigned kSpinLimit = 1u << 26;  // barrier polls (s_sleep 1 each) before giving up
 __device__ inline int xw(int x, int field) { return x * kXStride + field; }
 
 // Optional timing hooks (compiled in only with -DGF_TRACE, for profiling
@@ -198,12 +202,81 @@ __device__ void grid_sync(int32_t *ctl, unsigned nblocks) {
             __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins == kSpinLimit) {  // never expected: report and leave
+                    __hip_atomic_store(&ctl[G_TIMEOUT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+}
+
+// Grid barrier that also sums two per-workgroup values: a (the totals stay
+// below 2^32) and a flag (the number of workgroups that raise it).  Arrivals,
+// flag count and sum share one 64-bit word per XCD group and one at the top
+// (16 | 16 | 32 bits); the last arriver publishes the totals in the same
+// 64-bit word as the new generation, so no workgroup loads them afterwards.
+struct SyncSum {
+    unsigned a;
+    unsigned flags;
+};
+
+__device__ SyncSum grid_sync_sum(int32_t *ctl, unsigned nblocks, unsigned a, bool flag) {
+    __shared__ unsigned long long s_word;
+    typedef unsigned long long u64;
+    constexpr u64 kLow48 = (1ull << 48) - 1ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned x = blockIdx.x % kXcd;
+        const unsigned per_group = nblocks / kXcd;  // nblocks is a multiple of kXcd
+        u64 *gen = reinterpret_cast<u64 *>(&ctl[G_GEN2]);
+        u64 *top = reinterpret_cast<u64 *>(&ctl[G_TOP2]);
+        u64 *grp = reinterpret_cast<u64 *>(&ctl[xw((int)x, XF_SUM)]);
+        const u64 g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 48;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const u64 add = (1ull << 48) | ((u64)(flag ? 1u : 0u) << 32) | (u64)a;
+        const u64 prior = __hip_atomic_fetch_add(grp, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u64 word = 0;
+        bool have = false;
+        if ((prior >> 48) == per_group - 1) {
+            const u64 gsum = (prior + add) & kLow48;
+            __hip_atomic_store(grp, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const u64 tadd = (1ull << 48) | gsum;
+            const u64 tprior = __hip_atomic_fetch_add(top, tadd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((tprior >> 48) == kXcd - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(top, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                word = (((g + 1ull) & 0xffffull) << 48) | ((tprior + tadd) & kLow48);
+                __hip_atomic_store(gen, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                have = true;
+            }
+        }
+        if (!have) {
+            unsigned spins = 0;
+            for (;;) {
+                word = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((word >> 48) != g) break;
+                if (++spins == kSpinLimit) {  // never expected: report, publish nothing
+                    __hip_atomic_store(&ctl[G_TIMEOUT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    word = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_word = word;
+    }
+    __syncthreads();
+    const u64 w = s_word;
+    return SyncSum{(unsigned)(w & 0xffffffffull), (unsigned)((w >> 32) & 0xffffull)};
 }
 
 __device__ inline int ld_ctl(const int32_t *ctl, int i) {

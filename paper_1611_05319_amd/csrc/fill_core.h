@@ -100,9 +100,8 @@ template <int G> __device__ inline int gmin_i(int v) {
 // a shuffle; q_min is a |g|^2 times the smallest readable n^2.  The lattice
 // ball (no ghost pixels, or g = 0) evaluates exp per offset; that code runs
 // only in wavefronts that hold such a pixel.
-// The per-offset work is branch-free: the offset table is padded with entries
-// that are never readable and weigh 0, unreadable points contribute through
-// selects, and every load stays inside the view.
+// The geometry pass is branch-free: the offset table is padded with entries
+// that are never readable and weigh 0, and every load stays inside the view.
 // Returns true (on every lane of the group) when the pixel is ready; then
 // out[0..C) holds its new colour (FP64, before storage rounding).
 // (X, Y): the pixel in the view's coordinates; k: the shell used by the
@@ -125,7 +124,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     const int P = v.pitch();
     // pass 1: readable set and bilinear supports (kept for pass 2)
     float fxs[kPerLaneMax], fys[kPerLaneMax];
-    int base[kPerLaneMax], an[kPerLaneMax];
+    int base[kPerLaneMax];
     unsigned rmask = 0, exmask = 0, eymask = 0;
     int n2min = 0x7fffffff;    // rotated ball: smallest readable n^2
     double qmin_r = INFINITY;  // lattice ball: smallest readable exponent
@@ -149,11 +148,10 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         const bool rd = ins && (((int)readable(a0, k) & (int)readable(a1, k) &
                                  (int)readable(a2, k) & (int)readable(a3, k)) != 0);
         base[r] = b;
-        an[r] = abs((int)nm.x);
         rmask |= rd ? (1u << r) : 0u;
         exmask |= (ex || !rd) ? (1u << r) : 0u;  // unreadable points read one pixel
         eymask |= (ey || !rd) ? (1u << r) : 0u;
-        n2min = min(n2min, rd ? an[r] * an[r] : 0x7fffffff);
+        n2min = min(n2min, rd ? (int)nm.x * (int)nm.x : 0x7fffffff);
         if (lattice_here) {
             const double tp = (-gy) * ox + gx * oy;
             qmin_r = fmin(qmin_r, rd ? a * tp * tp : INFINITY);
@@ -193,7 +191,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
             const short2 nm = off[t];
             double w = 0.0;
             if (rot) {
-                w = __shfl(e_all, t < T ? an[r] : 0, G) * rinv[t];
+                w = __shfl(e_all, t < T ? abs((int)nm.x) : 0, G) * rinv[t];
             } else if (t < T) {
                 const double tp = (-gy) * (double)nm.x + gx * (double)nm.y;
                 w = exp(-(a * tp * tp - qmin_all)) * rinv[t];
@@ -211,32 +209,35 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
         const int t = l + r * G;
-        double e = __shfl(e_r, an[r] & (G - 1), G);  // every lane takes part
+        const short2 nm = off[t];
+        double e = __shfl(e_r, abs((int)nm.x) & (G - 1), G);  // every lane takes part
         if (lattice_here && !rot) {
-            const short2 nm = off[t];
             const double tp = (-gy) * (double)nm.x + gx * (double)nm.y;
             e = exp(-(a * tp * tp - qmin_r));
         }
-        const bool rd = (rmask >> r) & 1u;
-        const double w = rd ? e * rinv[t] : 0.0;
-        Ssum += w;
-        const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-        const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : P),
-                  i11 = i01 + (ex ? 0 : 1);
-        float c00[4], c10[4], c01[4], c11[4];
-        v.colours(i00, c00);
-        v.colours(i10, c10);
-        v.colours(i01, c01);
-        v.colours(i11, c11);
-        const float fx = fxs[r], fy = fys[r];
+        // neighbouring front pixels see the same side of the hole, so an offset
+        // is often unreadable for every pixel of a wavefront: the branch is
+        // then skipped as a whole
+        if ((rmask >> r) & 1u) {
+            const double w = e * rinv[t];
+            Ssum += w;
+            const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
+            const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : P),
+                      i11 = i01 + (ex ? 0 : 1);
+            float c00[4], c10[4], c01[4], c11[4];
+            v.colours(i00, c00);
+            v.colours(i10, c10);
+            v.colours(i01, c01);
+            v.colours(i11, c11);
+            const float fx = fxs[r], fy = fys[r];
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            if (ch < C) {
-                const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
-                const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
-                const float val = fmaf(fy, bot - top, top);
-                // an unreadable point may hold any bits (even NaN): select, do not scale
-                acc[ch] = rd ? fma(w, (double)val, acc[ch]) : acc[ch];
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ch < C) {
+                    const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
+                    const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
+                    const float val = fmaf(fy, bot - top, top);
+                    acc[ch] = fma(w, (double)val, acc[ch]);
+                }
             }
         }
     }

@@ -36,6 +36,8 @@ struct FillArgs {
 };
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
+constexpr int kAggMaxD = 4;    // adjoint: support patches up to (2*4+1)^2 pixels in LDS
+constexpr int kAggPatch = (2 * kAggMaxD + 1) * (2 * kAggMaxD + 1) * 4;  // floats per group
 
 // LDS staging of list appends: one global atomic per workgroup per flush
 struct Stage {
@@ -209,13 +211,12 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
     Stage lst{s_list, &s_list_n, kStageCap};
     Stage ord{s_ord, &s_ord_n, kStageCap};
     const bool want_order = A.order != nullptr;
-    int nk = ld_ctl(ctl, G_LIST + 0);
-    for (int k = 0; total_filled < total_hole; ++k) {
+    int nk = (int)min((long long)ld_ctl(ctl, G_LIST + 0), A.NP);
+    for (int k = 0; track || total_filled < total_hole; ++k) {
         if (A.max_shells > 0 && k >= A.max_shells) break;
         if (track && nk == 0) break;
         if (lw == 0 && tid == 0) {
             ctl[G_LIST + (k + 2) % 3] = 0;
-            ctl[G_FILL + (k + 1) % 3] = 0;
             ctl[G_ACTIVE + (k + 1) % 3] = 0;
         }
         int32_t *nxt_list = (k & 1) ? A.listA : A.listB;
@@ -319,39 +320,45 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
         }
         GF_TACC(1);
         if (my_fill) atomicAdd(&s_fill_n, my_fill);
+        __syncthreads();
+        const int appended = s_list_n;  // every push of this shell, staged or spilled
         if (track) stage_flush(lst, nxt_list, nxt_cnt, &s_base);
         if (want_order) stage_flush(ord, A.order, &ctl[G_ORDER], &s_base);
         __syncthreads();
+        const int wg_fill = s_fill_n, wg_active = s_active_n;
+        __syncthreads();
         if (tid == 0) {
-            if (s_fill_n) atomicAdd(&ctl[G_FILL + k % 3], s_fill_n);
-            if (!track && s_active_n) atomicAdd(&ctl[G_ACTIVE + k % 3], s_active_n);
+            if (wg_fill) atomicAdd(&ctl[G_FILLED], wg_fill);
+            if (!track && wg_active) atomicAdd(&ctl[G_ACTIVE + k % 3], wg_active);
             s_fill_n = 0;
             s_active_n = 0;
         }
         GF_TACC(2);
-        grid_sync(ctl, (unsigned)nblk);
+        // the barrier carries what every workgroup needs next: the length of the
+        // next front (tracked) or this shell's fills (untracked), and whether any
+        // workgroup filled a pixel
+        const SyncSum ss = grid_sync_sum(ctl, (unsigned)nblk, (unsigned)(track ? appended : wg_fill),
+                                         wg_fill != 0);
         GF_TACC(3);
         GF_TCNT(7, 1);
-        // independent loads, issued together (one round trip)
-        const int filled_k = ld_ctl(ctl, G_FILL + k % 3);
-        const int nk_next = ld_ctl(ctl, G_LIST + (k + 1) % 3);
-        const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + k % 3);
-        if (front_k > max_front) max_front = front_k;
-        if (lw == 0 && tid == 0) {
+        if (lw == 0 && tid == 0) {  // statistics: one workgroup loads what only it needs
+            const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + k % 3);
+            max_front = max(max_front, front_k);
             if (A.front_hist && k < A.kcap) A.front_hist[k] = front_k;
             if (want_order) {
                 if (k + 1 < A.kcap) A.shell_off[k + 1] = ld_ctl(ctl, G_ORDER);
                 else trunc = 1;
             }
         }
-        if (filled_k == 0) break;
-        total_filled += filled_k;
+        if (ss.flags == 0) break;  // nothing filled: done or stalled
         K = k + 1;
-        nk = nk_next;
+        if (track) nk = (int)min((long long)ss.a, A.NP);
+        else total_filled += ss.a;
         GF_TACC(4);
     }
 
     // ---- finish -------------------------------------------------------------
+    if (track) total_filled = ld_ctl(ctl, G_FILLED);
     if (total_filled < total_hole) {  // leftovers never became ready
         const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
         for (long long p = lo + tid; p < hi; p += kBlock) {
@@ -372,6 +379,7 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
         A.stats[3] = max_front;
         A.stats[4] = sum_x(ctl, XF_ERR);
         A.stats[5] = trunc;
+        A.stats[6] = ld_ctl(ctl, G_TIMEOUT);
     }
 }
 
@@ -406,7 +414,7 @@ struct BwdArgs {
 // ubar(x) w_j / S times the bilinear basis values into the support pixels.
 template <typename TS, int G>
 __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rinv, int T,
-                          long long gidx, float2 gv, int k, int l) {
+                          long long gidx, float2 gv, int k, int l, float *agg, int D) {
     const long long f = gidx / A.HW;
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
@@ -530,11 +538,54 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
             dgy += ub[ch] * (gsum<G>(Ay[ch]) - u * By + gsum<G>(Dy[ch])) * inv;
         }
     }
-    // pass 3: pass the adjoint to the bilinear supports
+    // pass 3: pass the adjoint to the bilinear supports.  With a small ball the
+    // contributions are first summed per support pixel in the group's LDS
+    // patch of (2D + 1)^2 pixels around x (D = ceil(eps) bounds every support
+    // offset), so each touched pixel takes one global atomic per channel
+    // instead of one per ghost point that reads it.
     const long long fo = f * A.HW;
+    if (agg) {
+        const int P2 = 2 * D + 1;
+        for (int i = l; i < P2 * P2 * C; i += G) agg[i] = 0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+        for (int r = 0; r < kPerLaneMax; ++r) {
+            if (rmask & (1u << r)) {
+                const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
+                const double lam = w[r] * inv;
+                const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
+                const int by = base[r] / W, bx = base[r] - by * W;
+                const int j00 = ((by - Y + D) * P2 + (bx - X + D)) * C;
+                const int j10 = j00 + (ex ? 0 : C), j01 = j00 + (ey ? 0 : P2 * C),
+                          j11 = j01 + (ex ? 0 : C);
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    if (ch < C) {
+                        const double g = ub[ch] * lam;
+                        atomicAdd(&agg[j00 + ch], (float)(g * wx0 * wy0));
+                        if (!ex) atomicAdd(&agg[j10 + ch], (float)(g * wx1 * wy0));
+                        if (!ey) atomicAdd(&agg[j01 + ch], (float)(g * wx0 * wy1));
+                        if (!ex && !ey) atomicAdd(&agg[j11 + ch], (float)(g * wx1 * wy1));
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int i = l; i < P2 * P2; i += G) {
+            const int yy = Y - D + i / P2, xx = X - D + i % P2;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ch < C) {
+                    const float v = agg[i * C + ch];
+                    // a nonzero sum only lands on a support pixel, inside the frame
+                    if (v != 0.0f) unsafeAtomicAdd(&GI[(fo + (long long)yy * W + xx) * C + ch], v);
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
-        if (rmask & (1u << r)) {
+        if (!agg && (rmask & (1u << r))) {
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
             const double lam = w[r] * inv;
             const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
@@ -566,6 +617,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
     __shared__ int s_T;
     __shared__ int s_item[kItemCap];
     __shared__ float2 s_gd[kItemCap];
+    __shared__ float s_agg[(kBlock / G) * kAggPatch];  // one support patch per group
     const int tid = threadIdx.x;
     const int nblk = (int)gridDim.x;
     const int lw = logical_block();
@@ -582,6 +634,8 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
     grid_sync(A.ctl, (unsigned)nblk);
     const int nG = kBlock / G;
     const int gi = tid / G, l = tid & (G - 1);
+    const int D = (int)ceil(A.eps);
+    const bool use_agg = D <= kAggMaxD && G <= 64;
     for (int k = A.K - 1; k >= 0; --k) {
         const long long b0 = A.shell_off[k], b1 = A.shell_off[k + 1];
         const long long n = b1 - b0;
@@ -597,7 +651,9 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
             __syncthreads();
             for (int base = 0; base < cn; base += nG) {
                 const int item = base + gi;
-                if (item < cn) bwd_pixel<TS, G>(A, s_off, s_rinv, T, s_item[item], s_gd[item], k, l);
+                if (item < cn)
+                    bwd_pixel<TS, G>(A, s_off, s_rinv, T, s_item[item], s_gd[item], k, l,
+                                     use_agg ? s_agg + gi * kAggPatch : nullptr, D);
             }
         }
         grid_sync(A.ctl, (unsigned)nblk);

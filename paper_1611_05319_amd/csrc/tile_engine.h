@@ -50,35 +50,7 @@ constexpr int kMaxWindow = 8192;     // window pixels (uint16 local lists)
 constexpr int kTileStageCap = 512;   // LDS staging of next-pass tiles per workgroup
 constexpr int kTileStaticLds = 8192; // bytes of static LDS the tile kernel may use
 
-constexpr int kCopyChunk = 16384;    // pixels per job of the deferred out-of-place copy
-
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-
-// Out-of-place form: every pixel that is not a hole pixel (label != 1) takes
-// its input colour; hole pixels are written by the fill (or, never filled, at
-// the end).  Pixels [p0, p1), four per thread per step, loads before stores.
-template <typename TS, int NT>
-__device__ void copy_known(const TS *in, TS *out, const uint8_t *label, int C, long long p0,
-                           long long p1) {
-    for (long long q = p0 + 4 * (long long)threadIdx.x; q < p1; q += 4 * (long long)NT) {
-        uint8_t lab[4];
-        TS v[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            lab[j] = q + j < p1 ? label[q + j] : (uint8_t)1;
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch)
-                if (ch < C && q + j < p1) v[j][ch] = in[(q + j) * C + ch];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (lab[j] != 1) {
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch)
-                    if (ch < C) out[(q + j) * C + ch] = v[j][ch];
-            }
-    }
-}
 
 // LDS of one window: states (int32), colours (storage type), guide (float2),
 // two local front lists (uint16)
@@ -104,7 +76,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     __shared__ int s_pass_fill, s_pass_kmax, s_hole_n, s_err_n;
     __shared__ int s_front_in[32];  // interior active pixels per local shell
     __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
-    __shared__ int s_job;           // deferred copy: the chunk taken
+    __shared__ int s_seg[kXcd];     // this pass's active-tile list length per XCD
 
     const int tid = threadIdx.x;
     const int nblk = (int)gridDim.x;
@@ -134,24 +106,13 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     Stage stage{s_stage, &s_stage_n, kTileStageCap};
     GF_T0();
 
-    // The out-of-place copy of known pixels is deferred: windows read original
-    // colours from the input, and the copy runs in chunks taken from a global
-    // counter by workgroups that have no tile in a pass, the rest at the end.
-    const long long ncopy = A.inplace ? 0 : (A.NP + kCopyChunk - 1) / kCopyChunk;
-    auto copy_jobs = [&](long long max_jobs) {
-        for (long long j = 0; j < max_jobs; ++j) {
-            __syncthreads();
-            if (tid == 0) s_job = atomicAdd(&ctl[G_COPY], 1);
-            __syncthreads();
-            const long long c = s_job;
-            if (c >= ncopy) break;  // uniform across the workgroup
-            const long long p0 = c * kCopyChunk, p1 = min(A.NP, p0 + kCopyChunk);
-            copy_known<TS, NT>(reinterpret_cast<const TS *>(A.in), reinterpret_cast<TS *>(A.out),
-                               A.label, C, p0, p1);
-        }
-    };
-
-    // ---- phase A: shell codes, per-tile hole counts, pass-0 tiles ------------
+    // ---- phase A: copy, shell codes, per-tile hole counts, pass-0 tiles ----
+    if (!A.inplace) {
+        const size_t esz = sizeof(TS) * (size_t)C;
+        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+        copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
+                   (size_t)lo * esz, (size_t)hi * esz);
+    }
     {
         const int tpx = A.TW * A.TH;
         int nb = (kWinPerThread * NT) / tpx;  // tiles per batch: <= kWinPerThread labels per thread
@@ -243,25 +204,19 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         int32_t *cur_act = (p & 1) ? A.act1 : A.act0;
         int32_t *nxt_act = ((p & 1) ? A.act0 : A.act1) + (long long)xcd * A.ntiles;
         int32_t *nxt_cnt = &ctl[xw(xcd, XF_ACT + (p + 1) % 3)];
-        int seg[kXcd];
-        int n_tiles_pass = 0;
-        if (A.tile_track) {
-#pragma unroll
-            for (int x = 0; x < kXcd; ++x) {
-                seg[x] = ld_ctl(ctl, xw(x, XF_ACT + p % 3));
-                n_tiles_pass += seg[x];
-            }
-        } else {
-            n_tiles_pass = A.ntiles;
-        }
+        if (A.tile_track && tid < kXcd) s_seg[tid] = ld_ctl(ctl, xw(tid, XF_ACT + p % 3));
         __syncthreads();
+        int n_tiles_pass = A.ntiles;
+        if (A.tile_track) {
+            n_tiles_pass = 0;
+#pragma unroll
+            for (int x = 0; x < kXcd; ++x) n_tiles_pass += s_seg[x];
+        }
         for (int v = lw; v < n_tiles_pass; v += nblk) {
             int t = v;
             if (A.tile_track) {
                 int i = v, x = 0;
-#pragma unroll
-                for (int xx = 0; xx < kXcd - 1; ++xx)
-                    if (x == xx && i >= seg[xx]) { i -= seg[xx]; x = xx + 1; }
+                while (x < kXcd - 1 && i >= s_seg[x]) i -= s_seg[x++];
                 t = cur_act[(long long)x * A.ntiles + i];
                 if (A.t_rem[t] == 0) continue;  // uniform across the workgroup
             }
@@ -269,19 +224,16 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             const int ox0 = tx * A.TW - A.Hh, oy0 = ty * A.TH - A.Hh;
             const int32_t *S = A.shell + (long long)f * A.HW;
             const TS *U = reinterpret_cast<const TS *>(A.out) + (long long)f * A.HW * C;
-            const TS *Uin = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
             const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
             // 1. stage the window in two round trips: states (readable before the
             //    pass / bystander / hole; pixels filled by neighbours during this pass
             //    count as hole), then colours of readable and guides of hole pixels
             for (int base = 0; base < WN; base += kWinPerThread * NT) {
                 int32_t code[kWinPerThread];
-                bool orig[kWinPerThread];  // known from the start: colour from the input
 #pragma unroll
                 for (int r = 0; r < kWinPerThread; ++r) {
                     const int i = base + tid + r * NT;
                     code[r] = S_BYSTANDER;
-                    orig[r] = false;
                     if (i < WN) {
                         const int wy = i / WW, wx = i - wy * WW;
                         const int x = ox0 + wx, y = oy0 + wy;
@@ -289,27 +241,6 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                             const int32_t s = S[y * W + x];
                             code[r] = (s == -1 || (s >= 0 && s < k0)) ? S_READABLE
                                       : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
-                            orig[r] = s == -1;
-                        }
-                    }
-                }
-                // every load of the second round trip is issued before the first
-                // LDS store that needs one
-                TS cv[kWinPerThread][4];
-                float2 gv[kWinPerThread];
-#pragma unroll
-                for (int r = 0; r < kWinPerThread; ++r) {
-                    const int i = base + tid + r * NT;
-                    if (i < WN) {
-                        const int wy = i / WW, wx = i - wy * WW;
-                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
-                        if (code[r] == S_READABLE) {
-                            const TS *src = orig[r] ? Uin : U;
-#pragma unroll
-                            for (int ch = 0; ch < 4; ++ch)
-                                if (ch < C) cv[r][ch] = src[q * C + ch];
-                        } else if (code[r] == S_HOLE) {
-                            gv[r] = Gd[q];
                         }
                     }
                 }
@@ -318,12 +249,12 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int i = base + tid + r * NT;
                     if (i < WN) {
                         st[i] = code[r];
+                        const int wy = i / WW, wx = i - wy * WW;
+                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
                         if (code[r] == S_READABLE) {
-#pragma unroll
-                            for (int ch = 0; ch < 4; ++ch)
-                                if (ch < C) col[i * CP + ch] = cv[r][ch];
+                            for (int ch = 0; ch < C; ++ch) col[i * CP + ch] = U[q * C + ch];
                         } else if (code[r] == S_HOLE) {
-                            gd[i] = gv[r];
+                            gd[i] = Gd[q];
                         }
                     }
                 }
@@ -510,7 +441,6 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             }
             GF_TACC(4);
         }
-        if (lw >= n_tiles_pass && ncopy) copy_jobs(2);  // no tile in this pass
         stage_flush(stage, nxt_act, nxt_cnt, &s_base);
         if (tid == 0 && s_pass_fill) {
             atomicAdd(&ctl[xw(xcd, XF_PFILL + p % 3)], s_pass_fill);
@@ -533,23 +463,15 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     }
 
     // ---- finish ---------------------------------------------------------------
-    if (ncopy) copy_jobs(ncopy);  // the rest of the deferred copy
-    if (total_filled < total_hole) {  // leftovers never became ready: shell -3, input colour
+    if (total_filled < total_hole) {  // leftovers never became ready: shell -3
         for (int t = lw; t < A.ntiles; t += nblk) {
             if (A.t_rem[t] == 0) continue;
             const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
             const int tw = min(A.TW, W - tx * A.TW), th = min(A.TH, H - ty * A.TH);
             int32_t *Sw = A.shell + (long long)f * A.HW;
-            const TS *Ui = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
-            TS *Uo = reinterpret_cast<TS *>(A.out) + (long long)f * A.HW * C;
             for (int i = tid; i < tw * th; i += NT) {
                 const int y = ty * A.TH + i / tw, x = tx * A.TW + i % tw;
-                if (Sw[y * W + x] == S_HOLE) {
-                    Sw[y * W + x] = S_UNFILLED;
-                    if (!A.inplace)
-                        for (int ch = 0; ch < C; ++ch)
-                            Uo[(long long)(y * W + x) * C + ch] = Ui[(long long)(y * W + x) * C + ch];
-                }
+                if (Sw[y * W + x] == S_HOLE) Sw[y * W + x] = S_UNFILLED;
             }
         }
     }
@@ -580,6 +502,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         A.stats[3] = max_front;
         A.stats[4] = sum_x(ctl, XF_ERR);
         A.stats[5] = 0;
+        A.stats[6] = ld_ctl(ctl, G_TIMEOUT);
     }
 }
 

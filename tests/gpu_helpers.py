@@ -46,6 +46,7 @@ def gpu_fill(img, label, guide, **kw):
     u = r.out.float().cpu().numpy().astype(np.float64)
     s = r.shell.cpu().numpy()
     st = r.host_stats()
+    assert not st["sync_timeout"], "a grid barrier gave up waiting"
     if not batched:
         u, s = u[0], s[0]
     return u, s, st, r

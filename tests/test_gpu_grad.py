@@ -34,7 +34,7 @@ def _frames(B, H, W, seed=5):
     return np.stack(imgs), lab, g, th
 
 
-def _compare(B, H, W, ghost=True, mu=50.0):
+def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0):
     import torch
 
     import paper_1611_05319_amd as gf
@@ -42,15 +42,15 @@ def _compare(B, H, W, ghost=True, mu=50.0):
     img, lab, g, th = _frames(B, H, W)
     rng = np.random.default_rng(77)
     omega = rng.normal(size=img.shape).astype(np.float32)
-    u, s, st, r = gpu_fill(img, lab, g, record_order=True, ghost=ghost, mu=mu)
+    u, s, st, r = gpu_fill(img, lab, g, record_order=True, ghost=ghost, mu=mu, eps=eps)
     gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g),
-                              gf.Params(eps=3.0, mu=mu, ghost=ghost))
+                              gf.Params(eps=eps, mu=mu, ghost=ghost))
     torch.cuda.synchronize()
     gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
-    ref = oracle.fill(img, lab, g, mu=mu, ghost=ghost)
+    ref = oracle.fill(img, lab, g, eps=eps, mu=mu, ghost=ghost)
     np.testing.assert_array_equal(s, ref.shell)
     # the oracle adjoint evaluated at the GPU's forward output (binary32 colours)
-    ri, rg = oracle.adjoint(lab, g, u, s, omega.astype(np.float64), mu=mu, ghost=ghost)
+    ri, rg = oracle.adjoint(lab, g, u, s, omega.astype(np.float64), eps=eps, mu=mu, ghost=ghost)
     for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
         err = np.abs(a - b)
         rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
@@ -61,9 +61,10 @@ def _compare(B, H, W, ghost=True, mu=50.0):
 
 
 @pytest.mark.parametrize("ghost", [True, False])
-def test_adjoint_small(ghost):
-    banner(f"adjoint 2 x 96 x 128 ghost={ghost}")
-    _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0)
+@pytest.mark.parametrize("eps", [3.0, 3.6, 5.0])  # patch sums for ceil(eps) <= 4, else direct
+def test_adjoint_small(ghost, eps):
+    banner(f"adjoint 2 x 96 x 128 ghost={ghost} eps={eps}")
+    _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0, eps=eps)
 
 
 def test_adjoint_config5_full():
