@@ -59,11 +59,12 @@ def problem_key(img: torch.Tensor, label: torch.Tensor, params: Params) -> str:
     B, H, W, C = img.shape
     frac = float((label == 1).sum().item()) / float(B * H * W)
     dev = torch.cuda.get_device_properties(img.device)
+    arch = getattr(dev, "gcnArchName", "") or "gpu"  # the marketing name can be empty
     order = "smart" if params.c >= 0 else "onion"
     return (f"{B}x{H}x{W}x{C}:{str(img.dtype).replace('torch.', '')}:eps={params.eps:g}:"
             f"mu={params.mu:g}:{order}:ghost={int(bool(params.ghost))}:"
             f"track={int(bool(params.tracking))}:hole={round(100 * frac)}%:"
-            f"{dev.name}:{dev.multi_processor_count}cu:lib={_library_digest()}")
+            f"{arch.split(':')[0]}:{dev.multi_processor_count}cu:lib={_library_digest()}")
 
 
 def candidates(img: torch.Tensor, params: Params) -> list[Params]:
