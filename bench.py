@@ -57,20 +57,26 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel_prefix):
+def launch_key(p):
+    """Canonical text of a launch shape, as recorded beside a counter summary."""
+    return (f"engine={p.engine} group={p.group} blocks_per_cu={p.blocks_per_cu} "
+            f"tile={p.tile_w}x{p.tile_h} pass_shells={p.pass_shells} tile_threads={p.tile_threads}")
+
+
+def recorded_traffic(params):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when it
-    is missing or was taken on other kernel sources."""
+    is missing, was taken on other kernel sources or another launch shape."""
     path = os.path.join(ROOT, "profiles", "traffic_c2_1080p.md")
     try:
         with open(path) as f:
             rec = dict(line.split(":", 1) for line in f.read().splitlines()
-                       if line.startswith(("source_sha256:", "kernel:", "traffic_bytes_per_launch:")))
+                       if line.startswith(("source_sha256:", "launch:", "traffic_bytes_per_launch:")))
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256", "").strip() != kernel_source_digest():
         return None
-    if not rec.get("kernel", "").strip().startswith(kernel_prefix):
+    if rec.get("launch", "").strip() != launch_key(params):
         return None
     try:
         return int(float(rec["traffic_bytes_per_launch"]))
@@ -208,8 +214,7 @@ def main():
                    "launch": launch_fields(params)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": recorded_traffic("tile_kernel" if params.engine == gf.ENGINE_TILED
-                                                 else "fill_kernel"),
+                     "traffic": recorded_traffic(params),
                      "algorithmic_bytes": nbytes, "event_ms_mean": round(ev_mean, 5),
                      "event_ms_median": round(ev_med, 5),
                      "us_per_shell": round(ev_mean * 1e3 / max(st["K"], 1), 3)},
