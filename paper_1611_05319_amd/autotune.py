@@ -91,8 +91,8 @@ def candidates(img: torch.Tensor, params: Params) -> list[Params]:
 
     rd = int(-(-params.eps // 1))  # ceil(eps): halo per shell
     add(engine=ENGINE_TILED)  # the library's own choice first
-    for S in (2, 3, 4, 6):
-        for tile in (16, 24, 32, 48):
+    for S in (2, 3, 4, 5, 6, 7, 8):
+        for tile in (16, 24, 32, 40, 48):
             if S * rd <= tile:
                 add(engine=ENGINE_TILED, tile_w=tile, tile_h=tile, pass_shells=S)
     add(engine=ENGINE_TILED, group=16)

@@ -292,6 +292,17 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             }
             GF_TACC(2);
             LdsView<TS> view{st, col, WW, A.WH, C, CP};
+            // Chebyshev distance of a window pixel from the tile interior.  A
+            // result at distance d in local shell j reaches the interior no
+            // earlier than shell j + d / rd, so local shell j only computes
+            // pixels with d <= (S - 1 - j) rd: the band shrinks by rd a shell
+            // and errors left outside it never reach the interior.
+            const int rd = A.Hh / A.S;
+            auto halo_dist = [&](int x, int y) {
+                const int dx = max(max(A.Hh - x, x - (A.Hh + A.TW - 1)), 0);
+                const int dy = max(max(A.Hh - y, y - (A.Hh + A.TH - 1)), 0);
+                return max(dx, dy);
+            };
             int cur = 0;
             for (int j = 0; j < Sp; ++j) {
                 // fill one window pixel with a group; returns ready, sets the counters
@@ -318,26 +329,31 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     GF_TCNT(8, 1);
                     const uint16_t *list = fl + cur * WN;
                     uint16_t *nlist = fl + (cur ^ 1) * WN;
+                    const int band = (Sp - 1 - j) * rd;
                     for (int base = 0; base < n; base += nG) {
                         const int item = base + gi;
                         int push = -1;
                         bool filled_here = false, interior = false;
                         if (item < n) {
                             const int wi = list[item];
-                            const bool ok = fill_one(wi, filled_here, interior);
-                            if (ok) {
-                                if (l < 8) {  // emit unfilled 8-neighbours, CAS dedup
-                                    const int d = l < 4 ? l : l + 1;
-                                    const int Y = wi / WW, X = wi - Y * WW;
-                                    const int xx = X + d % 3 - 1, yy = Y + d / 3 - 1;
-                                    if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH) {
-                                        const int nw = yy * WW + xx;
-                                        if (st[nw] == S_HOLE && atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
-                                            push = nw;
+                            const int Y = wi / WW, X = wi - Y * WW;
+                            if (halo_dist(X, Y) <= band) {  // else it cannot reach the interior
+                                const bool ok = fill_one(wi, filled_here, interior);
+                                if (ok) {
+                                    if (l < 8) {  // emit unfilled 8-neighbours, CAS dedup
+                                        const int d = l < 4 ? l : l + 1;
+                                        const int xx = X + d % 3 - 1, yy = Y + d / 3 - 1;
+                                        if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH &&
+                                            halo_dist(xx, yy) <= band - rd) {
+                                            const int nw = yy * WW + xx;
+                                            if (st[nw] == S_HOLE &&
+                                                atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
+                                                push = nw;
+                                        }
                                     }
+                                } else if (l == 0) {
+                                    push = wi;  // not ready: carry over
                                 }
-                            } else if (l == 0) {
-                                push = wi;  // not ready: carry over
                             }
                         }
                         const int slot = wave_append(push >= 0, &s_fn[cur ^ 1]);
@@ -351,11 +367,13 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         bool act = false;
                         if (i < WN && st[i] == S_HOLE) {
                             const int wy = i / WW, wx = i - wy * WW;
+                            if (halo_dist(wx, wy) <= (Sp - 1 - j) * rd) {
 #pragma unroll
-                            for (int d = 0; d < 9; ++d) {
-                                const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
-                                if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
-                                    act |= readable(st[yy * WW + xx], j);
+                                for (int d = 0; d < 9; ++d) {
+                                    const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
+                                    if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
+                                        act |= readable(st[yy * WW + xx], j);
+                                }
                             }
                         }
                         unsigned long long mask = __ballot(act);
