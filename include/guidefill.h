@@ -31,6 +31,10 @@
  *     shell k, -3 never filled (input colour kept).
  *   - Frames are independent; one call fills all of them.
  *   - Calls that share a workspace must not overlap in time.
+ *   - Workspaces: device memory, 256-byte aligned, owned by the caller, zeroed
+ *     before their first use; afterwards the library keeps them consistent
+ *     (each launch starts with a handshake on a per-workspace epoch number
+ *     that the library draws on the host).
  */
 #ifndef GUIDEFILL_H
 #define GUIDEFILL_H
@@ -92,8 +96,8 @@ enum {
 
 /*
  * Bytes of workspace gf_fill_batched needs for B frames of H x W (front lists,
- * control words).  The workspace is device memory, any content, 256-byte
- * aligned.
+ * control words).  The workspace is device memory, 256-byte aligned, zeroed
+ * before its first use (see the conventions above).
  */
 size_t gf_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
 

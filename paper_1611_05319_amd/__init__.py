@@ -203,7 +203,7 @@ class Workspace:
 
     def get(self, nbytes: int, device) -> torch.Tensor:
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
-            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self.buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
         return self.buf
 
 
@@ -305,7 +305,7 @@ def fill_backward(grad_out: torch.Tensor, fwd: FillResult, label: torch.Tensor,
     cp = p.c_struct()
     dt = _dtype_code(img_out)
     nbytes = lib.gf_backward_workspace_size(B, H, W, C, dt, ctypes.byref(cp))
-    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
     rc = lib.gf_fill_backward(_ptr(grad_out), _ptr(img_out), B, H, W, C, dt, _ptr(label),
                               _ptr(guide), _ptr(shell), _ptr(fwd.order), _ptr(fwd.shell_offsets),
                               int(K), ctypes.byref(cp), _ptr(grad_img), _ptr(grad_guide), _ptr(ws),
@@ -342,7 +342,7 @@ class FillPlan:
         self._dt = _dtype_code(img)
         lib = load()
         nbytes = lib.gf_workspace_size(B, H, W, C, self._dt, ctypes.byref(self._cp))
-        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        self.ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
         self._lib = lib
         self._args = (_ptr(img), _ptr(self.out), B, H, W, C, self._dt, _ptr(label), _ptr(guide),
                       ctypes.byref(self._cp), _ptr(self.shell), _ptr(self.stats),
@@ -373,7 +373,7 @@ class BackwardPlan:
         lib = load()
         self._cp = fwd.params.c_struct()
         nbytes = lib.gf_backward_workspace_size(B, H, W, C, fwd._dt, ctypes.byref(self._cp))
-        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=fwd.device)
+        self.ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=fwd.device)
         self._lib = lib
         self._args = (_ptr(grad_out), _ptr(fwd.out), B, H, W, C, fwd._dt, _ptr(fwd.label),
                       _ptr(fwd.guide), _ptr(fwd.shell), _ptr(fwd.order), _ptr(fwd.offsets), int(K),

@@ -46,6 +46,7 @@ enum : int {
     G_TOP2 = 640,   // 64-bit: counting barrier, arrivals of XCD groups and their sums
     G_GEN2 = 672,   // 64-bit: counting barrier, generation and the published sums
     G_TIMEOUT = 704,// set when a barrier wait exceeded its spin limit
+    G_READY = 736,  // epoch of the launch whose start-up is complete (never zeroed)
 };
 constexpr int XF_SUM = 10;  // 64-bit per-XCD word of the counting barrier (even index)
 constexpr unsigned kSpinLimit = 1u << 26;  // barrier polls (s_sleep 1 each) before giving up
@@ -277,6 +278,40 @@ __device__ SyncSum grid_sync_sum(int32_t *ctl, unsigned nblocks, unsigned a, boo
     __syncthreads();
     const u64 w = s_word;
     return SyncSum{(unsigned)(w & 0xffffffffull), (unsigned)((w >> 32) & 0xffffull)};
+}
+
+// Launch start-up: logical workgroup 0 zeroes the control block and the
+// caller's accumulated outputs, then publishes this launch's epoch (a number
+// the host never reuses for the workspace); every other workgroup waits for
+// it before touching any of them.  This replaces a separate clearing kernel,
+// whose dispatch gap before a cooperative launch costs more than the wait.
+__device__ void launch_start(int32_t *ctl, unsigned epoch, int32_t *z1, int n1, int32_t *z2, int n2,
+                             int32_t *z3, int n3) {
+    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+    const int n = (int)gridDim.x, b = (int)blockIdx.x;
+    const bool first = (b % kXcd) * (n / kXcd) + b / kXcd == 0;  // logical workgroup 0
+    if (first) {
+        for (int i = tid; i < kCtlWords; i += nt)
+            if (i != G_READY) ctl[i] = 0;
+        for (int i = tid; i < n1; i += nt) z1[i] = 0;
+        for (int i = tid; i < n2; i += nt) z2[i] = 0;
+        for (int i = tid; i < n3; i += nt) z3[i] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&ctl[G_READY], (int32_t)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        if (tid == 0) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctl[G_READY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                   (int32_t)epoch) {
+                if (++spins == kSpinLimit) break;  // the timeout flag cannot be trusted yet
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
 }
 
 __device__ inline int ld_ctl(const int32_t *ctl, int i) {

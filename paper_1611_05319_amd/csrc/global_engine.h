@@ -33,6 +33,7 @@ struct FillArgs {
     double a;  // mu^2 / (2 eps^2)
     double c;  // < 0 onion
     int ghost;
+    unsigned epoch;  // launch start-up handshake
 };
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
@@ -133,6 +134,8 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
     const int nblk = (int)gridDim.x;
     const int lw = logical_block();
     const int xcd = (int)(blockIdx.x % kXcd);
+    launch_start(A.ctl, A.epoch, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
+                 A.shell_off, A.shell_off ? 1 : 0);
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     if (tid == 0) s_list_n = s_ord_n = s_fill_n = s_active_n = s_hole_n = s_err_n = 0;
     for (int i = tid; i < kFrameCap; i += kBlock) {
@@ -403,6 +406,7 @@ struct BwdArgs {
     double eps;
     double a;
     int ghost;
+    unsigned epoch;  // launch start-up handshake
 };
 
 // Adjoint of one filled pixel x (shell k), one pass over its ball:
@@ -621,6 +625,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
     const int tid = threadIdx.x;
     const int nblk = (int)gridDim.x;
     const int lw = logical_block();
+    launch_start(A.ctl, A.epoch, nullptr, 0, nullptr, 0, nullptr, 0);
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     __syncthreads();
     const int T = s_T;

@@ -7,8 +7,8 @@
 //   GF_ENGINE_FRONT   one grid barrier per shell, the front as a global list
 //                     (global_engine.h); also records the fill order the
 //                     adjoint replays.
-// Both run as one cooperative persistent launch after a one-block prep
-// kernel that zeroes the control words and the stats.
+// Both run as one cooperative persistent launch; its first workgroup zeroes
+// the control words and the stats while the others wait for it.
 //
 // All arithmetic of the fill is FP64: the ghost offsets must be bit-identical
 // to the reference (points that land on lattice lines change the readable
@@ -23,7 +23,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <mutex>
+#include <unordered_map>
 
 #include "guidefill.h"
 #include "tile_engine.h"
@@ -32,14 +34,28 @@ using namespace gfk;
 
 namespace {
 
-__global__ void prep_kernel(int32_t *ctl, int32_t *stats, int nstats, int32_t *shell_off,
-                            int32_t *hist, int nhist) {
-    for (int i = threadIdx.x; i < kCtlWords; i += blockDim.x) ctl[i] = 0;
-    if (stats)
-        for (int i = threadIdx.x; i < nstats; i += blockDim.x) stats[i] = 0;
-    if (hist)
-        for (int i = threadIdx.x; i < nhist; i += blockDim.x) hist[i] = 0;
-    if (threadIdx.x == 0 && shell_off) shell_off[0] = 0;
+// Launch epochs per workspace: a value the workspace's control block has not
+// held (the kernels' start-up handshake waits for it).  The first epoch of a
+// workspace is drawn from the clock and the address, so stale or arbitrary
+// content is unlikely to match it; it is never 0 (a zeroed workspace).
+unsigned next_epoch(const void *ws) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, unsigned> epochs;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = epochs.find(ws);
+    unsigned e;
+    if (it == epochs.end()) {
+        const unsigned long long t =
+            (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count();
+        const unsigned long long p = (unsigned long long)(uintptr_t)ws;
+        e = (unsigned)((t ^ (t >> 32) ^ (p >> 8) ^ (p >> 40)) * 2654435761u);
+        epochs.emplace(ws, e);
+        it = epochs.find(ws);
+    }
+    e = it->second + 1u;
+    if (e == 0u) e = 1u;
+    it->second = e;
+    return e;
 }
 
 thread_local char g_last_error[512] = "";
@@ -360,10 +376,7 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     char *ws = reinterpret_cast<char *>(workspace);
     int32_t *ctl = reinterpret_cast<int32_t *>(ws + L.ctl);
     const double a = p->mu * p->mu / (2.0 * p->eps * p->eps);
-    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, s, ctl, stats, 8 + 4 * B, shell_offsets,
-                       front_hist, front_hist ? kcap : 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) { set_err("prep launch", e); return GF_EDEVICE; }
+    const unsigned epoch = next_epoch(workspace);
     if (p->engine == GF_ENGINE_FRONT) {
         FillArgs A;
         A.in = img_in;
@@ -392,6 +405,7 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
         A.a = a;
         A.c = p->c;
         A.ghost = p->ghost ? 1 : 0;
+        A.epoch = epoch;
         if (dt == GF_F32) return run_front<float>(A, G, p->blocks_per_cu, s);
         return run_front<__half>(A, G, p->blocks_per_cu, s);
     }
@@ -436,6 +450,7 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     A.eps = p->eps;
     A.a = a;
     A.c = p->c;
+    A.epoch = epoch;
     const int NT = tile_threads_of(p);
     if (dt == GF_F32) return run_tiled<float>(A, G, NT, p->blocks_per_cu, geom.lds, s);
     return run_tiled<__half>(A, G, NT, p->blocks_per_cu, geom.lds, s);
@@ -508,10 +523,7 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
     A.eps = p->eps;
     A.a = p->mu * p->mu / (2.0 * p->eps * p->eps);
     A.ghost = p->ghost ? 1 : 0;
-    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, s, A.ctl, (int32_t *)nullptr, 0,
-                       (int32_t *)nullptr, (int32_t *)nullptr, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) { set_err("prep launch", e); return GF_EDEVICE; }
+    A.epoch = next_epoch(workspace);
     if (dt == GF_F32) return run_bwd<float>(A, G, p->blocks_per_cu, s);
     return run_bwd<__half>(A, G, p->blocks_per_cu, s);
 }

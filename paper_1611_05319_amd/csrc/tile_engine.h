@@ -42,6 +42,7 @@ struct TileArgs {
     int tiles_x, tiles_y, ntiles;
     int max_shells, inplace, ghost, tile_track, local_track;
     double eps, a, c;
+    unsigned epoch;  // launch start-up handshake
 };
 
 
@@ -92,6 +93,8 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                                                 align16((size_t)WN * CP * sizeof(TS)) +
                                                 align16((size_t)WN * 8));
     int32_t *ctl = A.ctl;
+    launch_start(ctl, A.epoch, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
+                 nullptr, 0);
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     if (tid == 0) {
         s_stage_n = 0;
