@@ -114,7 +114,9 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     const bool rot = ghost && (gx != 0.0 || gy != 0.0);
     const bool lattice_here = __any(!rot);  // wavefront-uniform
     const double L2 = gx * gx + gy * gy;
-    double cs = 0.0, sn = 0.0;
+    // R takes (0, 1) to g/|g|; the lattice ball is R = identity, (c, s) = (0, 1),
+    // which the same products give exactly (n * 1 + m * 0 = n, m * 1 - n * 0 = m)
+    double cs = 0.0, sn = 1.0;
     if (rot) {
         const double L = sqrt(L2);
         cs = gx / L;
@@ -133,7 +135,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         const int t = l + r * G;
         const short2 nm = off[t];
         double ox, oy;
-        rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+        rot_offset(true, cs, sn, nm.x, nm.y, ox, oy);
         const double fx0 = floor(ox), fy0 = floor(oy);
         const bool ex = (ox == fx0), ey = (oy == fy0);
         const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
