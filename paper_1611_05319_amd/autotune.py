@@ -96,6 +96,13 @@ def candidates(img: torch.Tensor, params: Params) -> list[Params]:
             if S * rd <= tile:
                 add(engine=ENGINE_TILED, tile_w=tile, tile_h=tile, pass_shells=S)
     add(engine=ENGINE_TILED, group=16)
+    # 4-lane groups (8 offsets per lane) where the ball fits: eps < 4, <= 32 offsets
+    if params.eps < 4.0:
+        for nt in (0, 512):
+            for S in (4, 6):
+                if S * rd <= 32:
+                    add(engine=ENGINE_TILED, group=4, tile_threads=nt, tile_w=32, tile_h=32,
+                        pass_shells=S)
     # 512-thread workgroups: twice the registers per lane of the 1024-thread form
     for S in (2, 3, 4, 6):
         for tile in (24, 32, 48):

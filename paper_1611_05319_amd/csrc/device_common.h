@@ -16,7 +16,10 @@ namespace gfk {
 constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
 constexpr int kMaxOffsets = 256;  // eps <= 9: 252 offsets
 constexpr int kPadOffset = 16384; // (n, m) of the padding entries of the offset table
-constexpr int kPerLaneMax = 4;    // ball offsets handled by one lane
+constexpr int kPerLaneMax = 4;    // ball offsets handled by one lane (8 with 4-lane groups)
+// offsets per lane for a group of G lanes: 4-lane groups take a whole
+// eps <= 3 ball (28 offsets) in 7 steps, wider groups at most 4 per lane
+template <int G> __host__ __device__ constexpr int per_lane() { return G <= 4 ? 8 : kPerLaneMax; }
 constexpr int kStageCap = 2048;   // LDS staging entries per workgroup
 constexpr int kFrameCap = 64;     // frames with LDS statistics accumulators (global engine)
 constexpr int kXcd = 8;           // XCDs of the MI355X; workgroups are dealt round robin
@@ -70,10 +73,22 @@ __device__ long long gf_trace[4096 * kTraceSlots];
     do {                                                                                \
         if (threadIdx.x == 0) gf_trace[blockIdx.x * kTraceSlots + (slot)] += (v);       \
     } while (0)
+// register accumulators (no memory traffic inside loops), flushed once
+#define GF_RT_DECL(name) long long name = 0, name##_t0 = 0
+#define GF_RT_BEGIN(name) name##_t0 = wall_clock64()
+#define GF_RT_END(name) name += wall_clock64() - name##_t0
+#define GF_RT_FLUSH(slot, name)                                                         \
+    do {                                                                                \
+        if (threadIdx.x == 0) gf_trace[blockIdx.x * kTraceSlots + (slot)] += name;      \
+    } while (0)
 #else
 #define GF_T0()
 #define GF_TACC(slot)
 #define GF_TCNT(slot, v)
+#define GF_RT_DECL(name)
+#define GF_RT_BEGIN(name)
+#define GF_RT_END(name)
+#define GF_RT_FLUSH(slot, name)
 #endif
 
 // shell-map and window codes

@@ -106,7 +106,8 @@ template <int G> __device__ inline int gmin_i(int v) {
 // out[0..C) holds its new colour (FP64, before storage rounding).
 // (X, Y): the pixel in the view's coordinates; k: the shell used by the
 // readable test (s in [-1, k-1]); a = mu^2 / (2 eps^2); c < 0: onion order;
-// R = floor(eps) < G; off / rinv: the padded offset table (4 G entries).
+// R = floor(eps) < G; off / rinv: the padded offset table (per_lane<G>() * G
+// entries).
 template <typename TS, int G, typename V>
 __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool ghost,
                           const short2 *off, const double *rinv, int T, int R, int k, int l,
@@ -125,13 +126,14 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     const double aL2 = a * L2;
     const int P = v.pitch();
     // pass 1: readable set and bilinear supports (kept for pass 2)
-    float fxs[kPerLaneMax], fys[kPerLaneMax];
-    int base[kPerLaneMax];
+    constexpr int PL = per_lane<G>();
+    float fxs[PL], fys[PL];
+    int base[PL];
     unsigned rmask = 0, exmask = 0, eymask = 0;
     int n2min = 0x7fffffff;    // rotated ball: smallest readable n^2
     double qmin_r = INFINITY;  // lattice ball: smallest readable exponent
 #pragma unroll
-    for (int r = 0; r < kPerLaneMax; ++r) {
+    for (int r = 0; r < PL; ++r) {
         const int t = l + r * G;
         const short2 nm = off[t];
         double ox, oy;
@@ -176,7 +178,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         } else {
             double qm = INFINITY;
 #pragma unroll
-            for (int r = 0; r < kPerLaneMax; ++r) {
+            for (int r = 0; r < PL; ++r) {
                 const int t = l + r * G;
                 if (t < T) {
                     const short2 nm = off[t];
@@ -188,7 +190,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         }
         double num = 0.0, den = 0.0;
 #pragma unroll
-        for (int r = 0; r < kPerLaneMax; ++r) {
+        for (int r = 0; r < PL; ++r) {
             const int t = l + r * G;
             const short2 nm = off[t];
             double w = 0.0;
@@ -209,7 +211,7 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     double Ssum = 0.0, acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int C = v.C;
 #pragma unroll
-    for (int r = 0; r < kPerLaneMax; ++r) {
+    for (int r = 0; r < PL; ++r) {
         const int t = l + r * G;
         const short2 nm = off[t];
         double e = __shfl(e_r, abs((int)nm.x) & (G - 1), G);  // every lane takes part

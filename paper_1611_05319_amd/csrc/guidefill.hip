@@ -113,8 +113,10 @@ gf_status validate(const gf_params *p, int B, int H, int W, int C, gf_dtype dt) 
     if (!(p->c == p->c)) return GF_EINVAL;
     if (p->max_shells < 0) return GF_EINVAL;
     if (p->engine != GF_ENGINE_TILED && p->engine != GF_ENGINE_FRONT) return GF_EINVAL;
-    if (p->group != 0 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
+    if (p->group != 0 && p->group != 4 && p->group != 8 && p->group != 16 && p->group != 32 &&
+        p->group != 64)
         return GF_EINVAL;
+    if (p->group == 4 && p->engine != GF_ENGINE_TILED) return GF_EINVAL;
     if (p->blocks_per_cu < 0 || p->blocks_per_cu > 8) return GF_EINVAL;
     if (p->tile_w < 0 || p->tile_h < 0 || p->tile_w > 256 || p->tile_h > 256) return GF_EINVAL;
     if (p->pass_shells < 0 || p->pass_shells > 32) return GF_EINVAL;
@@ -253,6 +255,7 @@ template <typename TS, int NT>
 gf_status run_tiled_nt(const TileArgs &A, int G, int bpc, size_t lds, hipStream_t s) {
     const long long mb = 1ll << 30;
     if (bpc == 0) bpc = 8;  // as many workgroups per CU as the LDS and registers allow
+    if (G == 4) return launch_coop(tile_kernel<TS, 4, NT>, &A, bpc, mb, lds, s, NT);
     if (G == 8) return launch_coop(tile_kernel<TS, 8, NT>, &A, bpc, mb, lds, s, NT);
     if (G == 16) return launch_coop(tile_kernel<TS, 16, NT>, &A, bpc, mb, lds, s, NT);
     if (G == 32) return launch_coop(tile_kernel<TS, 32, NT>, &A, bpc, mb, lds, s, NT);
@@ -366,7 +369,8 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     if (order_out && p->engine != GF_ENGINE_FRONT) return GF_EUNSUPPORTED;
     const int T = count_offsets(p->eps);
     const int G = pick_group(p, T);
-    if (T > G * kPerLaneMax || T > kMaxOffsets) return GF_EUNSUPPORTED;
+    const int PL = G <= 4 ? per_lane<4>() : kPerLaneMax;
+    if (T > G * PL || T > kMaxOffsets || (int)floor(p->eps) >= G) return GF_EUNSUPPORTED;
     WsLayout L;
     TileGeom geom;
     int tiles_x = 0, tiles_y = 0;

@@ -108,6 +108,8 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     const int tpf = A.tiles_x * A.tiles_y;  // tiles per frame
     Stage stage{s_stage, &s_stage_n, kTileStageCap};
     GF_T0();
+    GF_RT_DECL(rt_fill);
+    GF_RT_DECL(rt_sync);
 
     // ---- phase A: copy, shell codes, per-tile hole counts, pass-0 tiles ----
     if (!A.inplace) {
@@ -333,34 +335,46 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const uint16_t *list = fl + cur * WN;
                     uint16_t *nlist = fl + (cur ^ 1) * WN;
                     const int band = (Sp - 1 - j) * rd;
+                    constexpr int kEmit = G < 8 ? 8 / G : 1;  // neighbours per lane
                     for (int base = 0; base < n; base += nG) {
                         const int item = base + gi;
-                        int push = -1;
+                        int push[kEmit];
+#pragma unroll
+                        for (int e = 0; e < kEmit; ++e) push[e] = -1;
                         bool filled_here = false, interior = false;
                         if (item < n) {
                             const int wi = list[item];
                             const int Y = wi / WW, X = wi - Y * WW;
                             if (halo_dist(X, Y) <= band) {  // else it cannot reach the interior
+                                GF_RT_BEGIN(rt_fill);
                                 const bool ok = fill_one(wi, filled_here, interior);
+                                GF_RT_END(rt_fill);
                                 if (ok) {
-                                    if (l < 8) {  // emit unfilled 8-neighbours, CAS dedup
-                                        const int d = l < 4 ? l : l + 1;
-                                        const int xx = X + d % 3 - 1, yy = Y + d / 3 - 1;
-                                        if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH &&
-                                            halo_dist(xx, yy) <= band - rd) {
-                                            const int nw = yy * WW + xx;
-                                            if (st[nw] == S_HOLE &&
-                                                atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
-                                                push = nw;
+#pragma unroll
+                                    for (int e = 0; e < kEmit; ++e) {
+                                        const int dl = l + e * G;  // emit unfilled 8-neighbours, CAS dedup
+                                        if (dl < 8) {
+                                            const int d = dl < 4 ? dl : dl + 1;
+                                            const int xx = X + d % 3 - 1, yy = Y + d / 3 - 1;
+                                            if (xx >= 0 && xx < WW && yy >= 0 && yy < A.WH &&
+                                                halo_dist(xx, yy) <= band - rd) {
+                                                const int nw = yy * WW + xx;
+                                                if (st[nw] == S_HOLE &&
+                                                    atomicCAS(&st[nw], S_HOLE, S_FRONT) == S_HOLE)
+                                                    push[e] = nw;
+                                            }
                                         }
                                     }
                                 } else if (l == 0) {
-                                    push = wi;  // not ready: carry over
+                                    push[0] = wi;  // not ready: carry over
                                 }
                             }
                         }
-                        const int slot = wave_append(push >= 0, &s_fn[cur ^ 1]);
-                        if (push >= 0) nlist[slot] = (uint16_t)push;
+#pragma unroll
+                        for (int e = 0; e < kEmit; ++e) {
+                            const int slot = wave_append(push[e] >= 0, &s_fn[cur ^ 1]);
+                            if (push[e] >= 0) nlist[slot] = (uint16_t)push[e];
+                        }
                         wave_count(filled_here, &s_filled_j);
                         wave_count(interior, &s_front_in[j & 31]);
                     }
@@ -397,6 +411,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         }
                     }
                 }
+                GF_RT_BEGIN(rt_sync);
                 __syncthreads();
                 const int filled = s_filled_j;
                 __syncthreads();
@@ -406,6 +421,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                 }
                 cur ^= 1;
                 __syncthreads();
+                GF_RT_END(rt_sync);
                 if (filled == 0) break;  // the window can no longer change in this pass
             }
             GF_TACC(3);
@@ -484,6 +500,8 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     }
 
     // ---- finish ---------------------------------------------------------------
+    GF_RT_FLUSH(11, rt_fill);
+    GF_RT_FLUSH(13, rt_sync);
     if (total_filled < total_hole) {  // leftovers never became ready: shell -3
         for (int t = lw; t < A.ntiles; t += nblk) {
             if (A.t_rem[t] == 0) continue;

@@ -77,7 +77,7 @@ def _call(lib, params, B=1, H=8, W=8, C=3, dt=0, ptr=1 << 20, ws_bytes=1 << 20, 
 @pytest.mark.parametrize("field,value", [
     ("eps", 0.0), ("eps", 0.5), ("eps", 9.5), ("eps", float("nan")), ("mu", 0.0),
     ("mu", -1.0), ("mu", float("inf")), ("c", float("nan")), ("max_shells", -1),
-    ("group", 4), ("blocks_per_cu", 9), ("blocks_per_cu", -1), ("engine", 2), ("engine", -1),
+    ("group", 2), ("blocks_per_cu", 9), ("blocks_per_cu", -1), ("engine", 2), ("engine", -1),
     ("pass_shells", 33), ("pass_shells", -1), ("tile_w", 300), ("tile_h", -2),
     ("tile_threads", 128), ("tile_threads", 768), ("tile_threads", -256)])
 def test_bad_parameters_are_rejected(lib, field, value):
@@ -92,6 +92,9 @@ def test_tile_threads_only_with_the_tiled_engine(lib):
     import paper_1611_05319_amd as gf
 
     assert _call(lib, gf.Params(engine=gf.ENGINE_FRONT, tile_threads=256).c_struct()) == -1
+    assert _call(lib, gf.Params(engine=gf.ENGINE_FRONT, group=4).c_struct()) == -1
+    # 4 lanes hold at most 32 offsets and need floor(eps) < 4
+    assert _call(lib, gf.Params(group=4, eps=3.6).c_struct()) == -3
 
 
 @pytest.mark.parametrize("shape", [(0, 8, 8, 3), (1, 0, 8, 3), (1, 8, 0, 3), (1, 8, 8, 0),
