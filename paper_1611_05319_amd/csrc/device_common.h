@@ -147,14 +147,54 @@ template <> __device__ inline __half to_storage<__half>(double v) {
 // ---------------------------------------------------------------------------
 // group (G lanes) reductions
 
+// Groups of 4 and 8 lanes reduce with DPP lane moves (swap neighbours, swap
+// pairs within a quad, mirror the two quads of 8 lanes): a VALU operand
+// modifier instead of a round trip through the LDS crossbar.  Every step
+// pairs lanes symmetrically, so all lanes of the group end with the same
+// value.  Wider groups use shuffles.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror: lane i <-> 7 - i within 8
+
+template <int CTRL> __device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ inline double dpp_d(double v) {
+    const int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 template <int G> __device__ inline double gsum(double v) {
+    if constexpr (G == 4 || G == 8) {
+        v += dpp_d<kDppXor1>(v);
+        v += dpp_d<kDppXor2>(v);
+        if constexpr (G == 8) v += dpp_d<kDppHalfMirror>(v);
+    } else {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+        for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    }
     return v;
 }
 template <int G> __device__ inline double gmin(double v) {
+    if constexpr (G == 4 || G == 8) {
+        v = fmin(v, dpp_d<kDppXor1>(v));
+        v = fmin(v, dpp_d<kDppXor2>(v));
+        if constexpr (G == 8) v = fmin(v, dpp_d<kDppHalfMirror>(v));
+    } else {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+        for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+    }
+    return v;
+}
+template <int G> __device__ inline int gmin_i(int v) {
+    if constexpr (G == 4 || G == 8) {
+        v = min(v, dpp_i<kDppXor1>(v));
+        v = min(v, dpp_i<kDppXor2>(v));
+        if constexpr (G == 8) v = min(v, dpp_i<kDppHalfMirror>(v));
+    } else {
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
+    }
     return v;
 }
 

@@ -86,12 +86,6 @@ template <typename TS> struct LdsView {
     __device__ void colours(int i, float o[4]) const { lds_colours<TS>(col + i * CP, CP, o); }
 };
 
-template <int G> __device__ inline int gmin_i(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
-    return v;
-}
-
 // Weights are exp(-(q - q_min)) / |(n, m)|: relative to the largest readable
 // weight (the quotient is unchanged, nothing underflows), with the exact
 // distance of the unrotated offset.  With the rotated ball the exponent is
