@@ -147,14 +147,16 @@ template <> __device__ inline __half to_storage<__half>(double v) {
 // ---------------------------------------------------------------------------
 // group (G lanes) reductions
 
-// Groups of 4 and 8 lanes reduce with DPP lane moves (swap neighbours, swap
-// pairs within a quad, mirror the two quads of 8 lanes): a VALU operand
-// modifier instead of a round trip through the LDS crossbar.  Every step
-// pairs lanes symmetrically, so all lanes of the group end with the same
-// value.  Wider groups use shuffles.
+// Groups reduce with DPP lane moves inside a row of 16 lanes (swap
+// neighbours, swap pairs within a quad, mirror the two quads of 8, mirror the
+// row): VALU operand modifiers instead of round trips through the LDS
+// crossbar; the steps across rows (groups of 32 and 64) use shuffles.  Every
+// step pairs lanes symmetrically, so all lanes of the group end with the same
+// value.
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror: lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // row_mirror: lane i <-> 15 - i within 16
 
 template <int CTRL> __device__ inline int dpp_i(int v) {
     return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
@@ -164,37 +166,34 @@ template <int CTRL> __device__ inline double dpp_d(double v) {
     return __hiloint2double(hi, lo);
 }
 
-template <int G> __device__ inline double gsum(double v) {
-    if constexpr (G == 4 || G == 8) {
-        v += dpp_d<kDppXor1>(v);
-        v += dpp_d<kDppXor2>(v);
-        if constexpr (G == 8) v += dpp_d<kDppHalfMirror>(v);
-    } else {
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    }
+struct OpSum {
+    __device__ static double d(double a, double b) { return a + b; }
+};
+struct OpMin {
+    __device__ static double d(double a, double b) { return fmin(a, b); }
+    __device__ static int i(int a, int b) { return min(a, b); }
+};
+
+template <int G, typename Op> __device__ inline double greduce(double v) {
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group width");
+    v = Op::d(v, dpp_d<kDppXor1>(v));
+    v = Op::d(v, dpp_d<kDppXor2>(v));
+    if constexpr (G >= 8) v = Op::d(v, dpp_d<kDppHalfMirror>(v));
+    if constexpr (G >= 16) v = Op::d(v, dpp_d<kDppMirror>(v));
+    if constexpr (G >= 32) v = Op::d(v, __shfl_xor(v, 16, G));
+    if constexpr (G >= 64) v = Op::d(v, __shfl_xor(v, 32, G));
     return v;
 }
-template <int G> __device__ inline double gmin(double v) {
-    if constexpr (G == 4 || G == 8) {
-        v = fmin(v, dpp_d<kDppXor1>(v));
-        v = fmin(v, dpp_d<kDppXor2>(v));
-        if constexpr (G == 8) v = fmin(v, dpp_d<kDppHalfMirror>(v));
-    } else {
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
-    }
-    return v;
-}
+
+template <int G> __device__ inline double gsum(double v) { return greduce<G, OpSum>(v); }
+template <int G> __device__ inline double gmin(double v) { return greduce<G, OpMin>(v); }
 template <int G> __device__ inline int gmin_i(int v) {
-    if constexpr (G == 4 || G == 8) {
-        v = min(v, dpp_i<kDppXor1>(v));
-        v = min(v, dpp_i<kDppXor2>(v));
-        if constexpr (G == 8) v = min(v, dpp_i<kDppHalfMirror>(v));
-    } else {
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
-    }
+    v = min(v, dpp_i<kDppXor1>(v));
+    v = min(v, dpp_i<kDppXor2>(v));
+    if constexpr (G >= 8) v = min(v, dpp_i<kDppHalfMirror>(v));
+    if constexpr (G >= 16) v = min(v, dpp_i<kDppMirror>(v));
+    if constexpr (G >= 32) v = min(v, __shfl_xor(v, 16, G));
+    if constexpr (G >= 64) v = min(v, __shfl_xor(v, 32, G));
     return v;
 }
 
