@@ -114,7 +114,7 @@ def candidates(img: torch.Tensor, params: Params) -> list[Params]:
             if S * rd <= tile:
                 add(engine=ENGINE_TILED, tile_threads=256, tile_w=tile, tile_h=tile, pass_shells=S)
     add(engine=ENGINE_FRONT)
-    for g in (16, 32, 64):
+    for g in (8, 16, 32, 64):
         for bpc in (0, 1, 4):
             add(engine=ENGINE_FRONT, group=g, blocks_per_cu=bpc)
     return out

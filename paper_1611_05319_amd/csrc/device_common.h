@@ -18,8 +18,12 @@ constexpr int kMaxOffsets = 256;  // eps <= 9: 252 offsets
 constexpr int kPadOffset = 16384; // (n, m) of the padding entries of the offset table
 constexpr int kPerLaneMax = 4;    // ball offsets handled by one lane (8 with 4-lane groups)
 // offsets per lane for a group of G lanes: 4-lane groups take a whole
-// eps <= 3 ball (28 offsets) in 7 steps, wider groups at most 4 per lane
-template <int G> __host__ __device__ constexpr int per_lane() { return G <= 4 ? 8 : kPerLaneMax; }
+// eps <= 3 ball (28 offsets) in 7 steps, 16-lane groups an eps = 5 ball (80
+// offsets) in 5, other widths at most 4 per lane
+template <int G> __host__ __device__ constexpr int per_lane() {
+    return G <= 4 ? 8 : (G == 16 ? 5 : kPerLaneMax);
+}
+__host__ __device__ inline int per_lane_of(int G) { return G <= 4 ? 8 : (G == 16 ? 5 : kPerLaneMax); }
 constexpr int kStageCap = 2048;   // LDS staging entries per workgroup
 constexpr int kFrameCap = 64;     // frames with LDS statistics accumulators (global engine)
 constexpr int kXcd = 8;           // XCDs of the MI355X; workgroups are dealt round robin

@@ -369,8 +369,8 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     if (order_out && p->engine != GF_ENGINE_FRONT) return GF_EUNSUPPORTED;
     const int T = count_offsets(p->eps);
     const int G = pick_group(p, T);
-    const int PL = G <= 4 ? per_lane<4>() : kPerLaneMax;
-    if (T > G * PL || T > kMaxOffsets || (int)floor(p->eps) >= G) return GF_EUNSUPPORTED;
+    if (T > G * per_lane_of(G) || T > kMaxOffsets || (int)floor(p->eps) >= G)
+        return GF_EUNSUPPORTED;
     WsLayout L;
     TileGeom geom;
     int tiles_x = 0, tiles_y = 0;
@@ -503,7 +503,11 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
     gf_params q = *p;
     q.engine = GF_ENGINE_FRONT;
     const int T = count_offsets(p->eps);
-    const int G = pick_group(&q, T);
+    int G = pick_group(&q, T);
+    if (T > G * kPerLaneMax) {  // the forward's group may hold more offsets per lane
+        q.group = 0;
+        G = pick_group(&q, T);
+    }
     if (T > G * kPerLaneMax || T > kMaxOffsets) return GF_EUNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     BwdArgs A;

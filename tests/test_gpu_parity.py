@@ -325,3 +325,13 @@ def test_smart_order_threshold_on_a_straight_edge(engine):
     for c in (C0 * (1 - 1e-9), C0 * (1 + 1e-9)):
         ref, u, s, st, _ = _check(img, lab, g, eps=eps, mu=mu, c=c, **LAUNCH[engine])
         assert (s[4, W // 2] == 0) == (c < C0)
+
+
+@pytest.mark.parametrize("kw", [{"group": 16}, {"group": 16, "engine": 1}, {"group": 64},
+                                {"group": 16, "tracking": False}])
+def test_wide_ball_group_widths(kw):
+    # eps = 5 (80 offsets): 16 lanes x 5 offsets, 32 x 3, 64 x 2 per lane
+    banner(f"eps=5 group widths {kw}")
+    rng = np.random.default_rng(21)
+    img, lab, g = syn.random_tiny(rng, 90, 110, C=3, p_hole=0.4, p_bystander=0.05)
+    _check(img, lab, g, eps=5.0, mu=100.0, **kw)
