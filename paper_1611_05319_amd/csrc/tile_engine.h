@@ -222,8 +222,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             if (A.tile_track) {
                 int i = v, x = 0;
                 while (x < kXcd - 1 && i >= s_seg[x]) i -= s_seg[x++];
+                // a listed tile whose holes are all filled finds nothing to do; its
+                // remaining count is not checked first (one load fewer on the way in)
                 t = cur_act[(long long)x * A.ntiles + i];
-                if (A.t_rem[t] == 0) continue;  // uniform across the workgroup
             }
             const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
             const int ox0 = tx * A.TW - A.Hh, oy0 = ty * A.TH - A.Hh;
