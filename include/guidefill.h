@@ -74,7 +74,7 @@ typedef struct {
     int32_t tile_w, tile_h; /* tiled engine: tile interior in pixels, 0 = auto (<= 256) */
     int32_t pass_shells;    /* tiled engine: shells per grid sync, 0 = auto (<= 32); the halo
                                pass_shells * ceil(eps) may not exceed tile_w or tile_h */
-    int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (auto), 256, 512 or 1024;
+    int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (auto), 256, 512, 768, 1024;
                                must be 0 with GF_ENGINE_FRONT */
 } gf_params;
 

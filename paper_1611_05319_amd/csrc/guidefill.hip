@@ -121,7 +121,7 @@ gf_status validate(const gf_params *p, int B, int H, int W, int C, gf_dtype dt) 
     if (p->tile_w < 0 || p->tile_h < 0 || p->tile_w > 256 || p->tile_h > 256) return GF_EINVAL;
     if (p->pass_shells < 0 || p->pass_shells > 32) return GF_EINVAL;
     if (p->tile_threads != 0 && p->tile_threads != 256 && p->tile_threads != 512 &&
-        p->tile_threads != 1024)
+        p->tile_threads != 768 && p->tile_threads != 1024)
         return GF_EINVAL;
     if (p->tile_threads != 0 && p->engine != GF_ENGINE_TILED) return GF_EINVAL;
     long long np = (long long)B * H * W;
@@ -147,7 +147,7 @@ template <typename TS>
 bool tile_geometry(const gf_params *p, int C, size_t lds_limit, TileGeom &g) {
     const int rd = rdep_of(p->eps);
     const size_t static_lds = kTileStaticLds;  // staging buffer, offsets, counters
-    int S = p->pass_shells ? p->pass_shells : (rd <= 3 ? 4 : (rd <= 6 ? 3 : 2));
+    int S = p->pass_shells ? p->pass_shells : (rd <= 3 ? 6 : (rd <= 6 ? 3 : 2));
     for (;;) {
         const int Hh = S * rd;
         int TW = p->tile_w ? p->tile_w : (Hh > 32 ? Hh : 32);
@@ -266,6 +266,7 @@ template <typename TS>
 gf_status run_tiled(const TileArgs &A, int G, int NT, int bpc, size_t lds, hipStream_t s) {
     if (NT == 256) return run_tiled_nt<TS, 256>(A, G, bpc, lds, s);
     if (NT == 512) return run_tiled_nt<TS, 512>(A, G, bpc, lds, s);
+    if (NT == 768) return run_tiled_nt<TS, 768>(A, G, bpc, lds, s);
     return run_tiled_nt<TS, 1024>(A, G, bpc, lds, s);
 }
 

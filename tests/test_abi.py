@@ -79,7 +79,7 @@ def _call(lib, params, B=1, H=8, W=8, C=3, dt=0, ptr=1 << 20, ws_bytes=1 << 20, 
     ("mu", -1.0), ("mu", float("inf")), ("c", float("nan")), ("max_shells", -1),
     ("group", 2), ("blocks_per_cu", 9), ("blocks_per_cu", -1), ("engine", 2), ("engine", -1),
     ("pass_shells", 33), ("pass_shells", -1), ("tile_w", 300), ("tile_h", -2),
-    ("tile_threads", 128), ("tile_threads", 768), ("tile_threads", -256)])
+    ("tile_threads", 128), ("tile_threads", 640), ("tile_threads", -256)])
 def test_bad_parameters_are_rejected(lib, field, value):
     import paper_1611_05319_amd as gf
 

@@ -165,6 +165,7 @@ FORMS = [
     {"tile_w": 100, "tile_h": 120, "pass_shells": 2},
     {"tile_threads": 256}, {"tile_threads": 512}, {"tile_threads": 512, "pass_shells": 2},
     {"group": 4}, {"group": 4, "tile_threads": 512}, {"group": 4, "tracking": False},
+    {"tile_threads": 768}, {"tile_threads": 768, "group": 16, "pass_shells": 3},
     {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "pass_shells": 4},
     {"tile_threads": 256, "tile_w": 24, "tile_h": 12, "pass_shells": 2, "tracking": False},
     {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "group": 16},
