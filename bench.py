@@ -57,13 +57,20 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def launch_key(p):
-    """Canonical text of a launch shape, as recorded beside a counter summary."""
-    return (f"engine={p.engine} group={p.group} blocks_per_cu={p.blocks_per_cu} "
-            f"tile={p.tile_w}x{p.tile_h} pass_shells={p.pass_shells} tile_threads={p.tile_threads}")
+def launch_key(p, H, W, C):
+    """Canonical text of the launch shape the library resolves for these
+    parameters (automatic fields filled in), as recorded beside a counter
+    summary."""
+    import paper_1611_05319_amd as gf
+
+    if p.engine == gf.ENGINE_TILED:
+        tw, th, S, _, _, G = gf.tile_geometry(H, W, C, params=p)
+        return (f"engine=0 tile={tw}x{th} pass_shells={S} group={G} "
+                f"tile_threads={p.tile_threads or 1024} blocks_per_cu={p.blocks_per_cu}")
+    return f"engine=1 group={p.group} blocks_per_cu={p.blocks_per_cu}"
 
 
-def recorded_traffic(params):
+def recorded_traffic(params, H, W, C):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when it
     is missing, was taken on other kernel sources or another launch shape."""
@@ -76,7 +83,7 @@ def recorded_traffic(params):
         return None
     if rec.get("source_sha256", "").strip() != kernel_source_digest():
         return None
-    if rec.get("launch", "").strip() != launch_key(params):
+    if rec.get("launch", "").strip() != launch_key(params, H, W, C):
         return None
     try:
         return int(float(rec["traffic_bytes_per_launch"]))
@@ -214,7 +221,7 @@ def main():
                    "launch": launch_fields(params)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": recorded_traffic(params),
+                     "traffic": recorded_traffic(params, H, W, C),
                      "algorithmic_bytes": nbytes, "event_ms_mean": round(ev_mean, 5),
                      "event_ms_median": round(ev_med, 5),
                      "us_per_shell": round(ev_mean * 1e3 / max(st["K"], 1), 3)},
