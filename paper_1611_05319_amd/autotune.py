@@ -123,7 +123,8 @@ def candidates(img: torch.Tensor, params: Params) -> list[Params]:
 
 
 def _time(plan: FillPlan, reps: int) -> float:
-    plan.run()
+    for _ in range(3):  # first launches of a shape pay one-time costs
+        plan.run()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(reps)]

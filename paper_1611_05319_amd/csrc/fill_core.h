@@ -238,6 +238,8 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
                 }
             }
         }
+        // one offset's loads at a time: fewer registers live (no spills)
+        __builtin_amdgcn_sched_barrier(0);
     }
     Ssum = gsum<G>(Ssum);
     const double inv = 1.0 / Ssum;

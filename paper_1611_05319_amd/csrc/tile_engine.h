@@ -338,6 +338,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int band = (Sp - 1 - j) * rd;
                     constexpr int kEmit = G < 8 ? 8 / G : 1;  // neighbours per lane
                     for (int base = 0; base < n; base += nG) {
+                        int lt = tid;
+                        asm volatile("" : "+v"(lt));  // recompute lane values here, not hoisted
+                        const int gi = lt / G, l = lt & (G - 1);
                         const int item = base + gi;
                         int push[kEmit];
 #pragma unroll
