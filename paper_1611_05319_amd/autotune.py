@@ -117,7 +117,7 @@ def candidates(img: torch.Tensor, params: Params) -> list[Params]:
                 add(engine=ENGINE_TILED, tile_threads=256, tile_w=tile, tile_h=tile, pass_shells=S)
     add(engine=ENGINE_FRONT)
     for g in (8, 16, 32, 64):
-        for bpc in (0, 1, 4):
+        for bpc in (0, 1, 2, 3):
             add(engine=ENGINE_FRONT, group=g, blocks_per_cu=bpc)
     return out
 

@@ -113,8 +113,11 @@ __device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const do
     return true;
 }
 
+// three workgroups of 256 per CU (12 wavefronts): the register budget that
+// keeps the fill free of spills while holding more front pixels in flight;
+// two for 16-lane groups, whose 5 offsets per lane need more registers
 template <typename TS, int G>
-__global__ __launch_bounds__(kBlock) void fill_kernel(FillArgs A) {
+__global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs A) {
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
     __shared__ int s_T;

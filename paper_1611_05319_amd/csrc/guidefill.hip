@@ -242,6 +242,7 @@ gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long lo
 template <typename TS>
 gf_status run_front(const FillArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
+    if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers allow
     if (G == 8) return launch_coop(fill_kernel<TS, 8>, &A, bpc, mb, 0, s);
     if (G == 16) return launch_coop(fill_kernel<TS, 16>, &A, bpc, mb, 0, s);
     if (G == 32) return launch_coop(fill_kernel<TS, 32>, &A, bpc, mb, 0, s);
