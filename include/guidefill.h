@@ -34,7 +34,8 @@
  *   - Workspaces: device memory, 256-byte aligned, owned by the caller, zeroed
  *     before their first use; afterwards the library keeps them consistent
  *     (each launch starts with a handshake on a per-workspace epoch number
- *     that the library draws on the host).
+ *     that the library draws on the host for every call, so a call captured
+ *     into a graph must not be replayed).
  */
 #ifndef GUIDEFILL_H
 #define GUIDEFILL_H
