@@ -336,3 +336,28 @@ def test_wide_ball_group_widths(kw):
     rng = np.random.default_rng(21)
     img, lab, g = syn.random_tiny(rng, 90, 110, C=3, p_hole=0.4, p_bystander=0.05)
     _check(img, lab, g, eps=5.0, mu=100.0, **kw)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_more_frames_than_lds_statistics(engine):
+    # 70 small frames: the frames past the 64 with LDS statistics accumulators
+    # count through global atomics; every frame's map and statistics must
+    # equal its own single-frame fill
+    banner(f"70 frames engine={engine}")
+    rng = np.random.default_rng(70)
+    frames = [syn.random_tiny(rng, 24, 30, C=3, p_hole=rng.uniform(0.0, 0.7), p_bystander=0.05)
+              for _ in range(70)]
+    bi = np.stack([f[0] for f in frames])
+    bl = np.stack([f[1] for f in frames])
+    bg = np.stack([f[2] for f in frames])
+    ub, sb, stb, _ = gpu_fill(bi, bl, bg, **LAUNCH[engine])
+    K = 0
+    for i, (fi, fl, fg) in enumerate(frames):
+        ref = oracle.fill(fi, fl, fg)
+        np.testing.assert_array_equal(sb[i], ref.shell)
+        assert_colour_parity(ub[i], ref.u, ref.shell)
+        assert stb["frame_K"][i] == ref.K
+        assert stb["frame_filled"][i] == ref.n_filled
+        assert stb["frame_hole"][i] == int((fl == 1).sum())
+        K = max(K, ref.K)
+    assert stb["K"] == K
