@@ -273,30 +273,6 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             __syncthreads();
             GF_TACC(1);
             GF_TCNT(6, 1);
-            // 2. local shells
-            if (A.local_track) {
-                for (int i = tid; i < WN; i += NT) {
-                    if (st[i] != S_HOLE) continue;
-                    const int wy = i / WW, wx = i - wy * WW;
-                    bool act = false;
-#pragma unroll
-                    for (int d = 0; d < 9; ++d) {
-                        const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
-                        if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
-                            act |= (st[yy * WW + xx] == S_READABLE);
-                    }
-                    if (act) st[i] = S_FRONT;
-                }
-                __syncthreads();
-                for (int base = 0; base < WN; base += NT) {  // uniform trip count
-                    const int i = base + tid;
-                    const bool want = i < WN && st[i] == S_FRONT;
-                    const int slot = wave_append(want, &s_fn[0]);
-                    if (want) fl[slot] = (uint16_t)i;
-                }
-                __syncthreads();
-            }
-            GF_TACC(2);
             LdsView<TS> view{st, col, WW, A.WH, C, CP};
             // Chebyshev distance of a window pixel from the tile interior.  A
             // result at distance d in local shell j reaches the interior no
@@ -309,6 +285,31 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                 const int dy = max(max(A.Hh - y, y - (A.Hh + A.TH - 1)), 0);
                 return max(dx, dy);
             };
+            // 2. local shells; the first local front: hole pixels with a readable
+            //    8-neighbour inside the band that can still reach the interior,
+            //    marked and listed in one sweep
+            if (A.local_track) {
+                for (int base = 0; base < WN; base += NT) {  // uniform trip count
+                    const int i = base + tid;
+                    bool act = false;
+                    if (i < WN && st[i] == S_HOLE) {
+                        const int wy = i / WW, wx = i - wy * WW;
+                        if (halo_dist(wx, wy) <= (Sp - 1) * rd) {
+#pragma unroll
+                            for (int d = 0; d < 9; ++d) {
+                                const int xx = wx + d % 3 - 1, yy = wy + d / 3 - 1;
+                                if (d != 4 && xx >= 0 && xx < WW && yy >= 0 && yy < A.WH)
+                                    act |= (st[yy * WW + xx] == S_READABLE);
+                            }
+                        }
+                    }
+                    if (act) st[i] = S_FRONT;  // other lanes only test for S_READABLE
+                    const int slot = wave_append(act, &s_fn[0]);
+                    if (act) fl[slot] = (uint16_t)i;
+                }
+                __syncthreads();
+            }
+            GF_TACC(2);
             int cur = 0;
             for (int j = 0; j < Sp; ++j) {
                 // fill one window pixel with a group; returns ready, sets the counters
