@@ -34,8 +34,13 @@
  *   - Workspaces: device memory, 256-byte aligned, owned by the caller, zeroed
  *     before their first use; afterwards the library keeps them consistent
  *     (each launch starts with a handshake on a per-workspace epoch number
- *     that the library draws on the host for every call, so a call captured
- *     into a graph must not be replayed).
+ *     and join-word set that the library draws on the host for every call,
+ *     so a call captured into a graph must not be replayed).
+ *   - Each call is one persistent kernel launch: an ordinary (not
+ *     cooperative) launch of as many workgroups as the device holds at once.
+ *     The workgroups resident at start-up take part and any others leave at
+ *     once (stats[GF_STAT_WORKGROUPS] reports how many took part), so work
+ *     running concurrently on the device slows a call but cannot deadlock it.
  */
 #ifndef GUIDEFILL_H
 #define GUIDEFILL_H
@@ -91,6 +96,8 @@ enum {
     GF_STAT_ORDER_TRUNC = 5, /* 1 if shell_offsets was too short for K + 1 entries */
     GF_STAT_SYNC_TIMEOUT = 6,/* 1 if a grid barrier gave up waiting (never expected; the
                                 results are then invalid) */
+    GF_STAT_WORKGROUPS = 7,  /* workgroups that took part in the persistent launch (those
+                                resident at start-up; normally the whole launched grid) */
     GF_STAT_FRAME0 = 8,      /* then per frame f at 8 + 4 f: K_f, filled_f, hole_f, 0 */
     GF_STAT_PER_FRAME = 4
 };

@@ -35,7 +35,7 @@ _lock = threading.Lock()
 GF_F32, GF_F16 = 0, 1
 _STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "unsupported request"}
 (STAT_SHELLS, STAT_FILLED, STAT_HOLE, STAT_MAX_FRONT, STAT_LABEL_ERR, STAT_ORDER_TRUNC,
- STAT_SYNC_TIMEOUT) = range(7)
+ STAT_SYNC_TIMEOUT, STAT_WORKGROUPS) = range(8)
 STAT_FRAME0, STAT_PER_FRAME = 8, 4
 
 
@@ -190,6 +190,7 @@ def stats_fields(stats: torch.Tensor) -> dict:
         "unfilled": s[STAT_HOLE] - s[STAT_FILLED], "max_front": s[STAT_MAX_FRONT],
         "label_errors": s[STAT_LABEL_ERR], "order_truncated": bool(s[STAT_ORDER_TRUNC]),
         "sync_timeout": bool(s[STAT_SYNC_TIMEOUT]),
+        "workgroups": s[STAT_WORKGROUPS],
         "frame_K": [fr[0] for fr in frames], "frame_filled": [fr[1] for fr in frames],
         "frame_hole": [fr[2] for fr in frames],
     }

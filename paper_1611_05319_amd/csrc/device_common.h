@@ -39,6 +39,7 @@ enum : int {
     XF_KMAX = 7,    // largest shell + 1 filled so far
     XF_HOLE = 8,    // label-1 pixels
     XF_ERR = 9,     // label errors
+    XF_TICKET = 12, // [3] start-up join tickets of this XCD's workgroups, ring by launch slot
 };
 enum : int {
     G_GEN = 256,    // barrier generation
@@ -54,7 +55,11 @@ enum : int {
     G_GEN2 = 672,   // 64-bit: counting barrier, generation and the published sums
     G_TIMEOUT = 704,// set when a barrier wait exceeded its spin limit
     G_READY = 736,  // epoch of the launch whose start-up is complete (never zeroed)
+    G_LEAD = 768,   // [3] start-up leader election, ring by launch slot
+    G_NX = 800,     // [kXcd] workgroups taking part per XCD group, this launch
 };
+constexpr int kLaunchSlots = 3;         // join-word sets in the ring (see launch_start)
+constexpr unsigned kClosed = 1u << 30;  // join word: the poll is closed
 constexpr int XF_SUM = 10;  // 64-bit per-XCD word of the counting barrier (even index)
 constexpr unsigned kSpinLimit = 1u << 26;  // barrier polls (s_sleep 1 each) before giving up
 __device__ inline int xw(int x, int field) { return x * kXStride + field; }
@@ -227,20 +232,152 @@ __device__ inline void wave_count(bool pred, int *counter) {
 __device__ inline bool readable(int32_t s, int k) { return (unsigned)(s + 1) <= (unsigned)k; }
 
 // ---------------------------------------------------------------------------
-// grid barrier (all workgroups co-resident: cooperative launch).  Arrivals are
-// counted per XCD group first, then per group, so no counter sees more than
-// max(nblocks / 8, 8) serialised atomics.  Waves of a workgroup share the
+// Persistent launches without a cooperative dispatch.  The kernels are
+// launched as ordinary grids sized to what the device holds at once (the
+// cooperative dispatch costs ~17 us more per launch here).  Residency is then
+// not promised, so the workgroups that take part are discovered at start-up:
+// each one takes a ticket on its XCD group's join word; one leader waits until
+// every launched workgroup has joined, or at most join_ticks of the 100 MHz
+// constant clock, and closes the poll.  A workgroup that joins after the close
+// leaves at once, so every barrier waits only for workgroups that have run,
+// hence are resident.  Join words cannot be cleared after a launch (a late
+// workgroup may still add to them), so the host deals out kLaunchSlots sets in
+// a ring and each launch clears the next launch's set.
+
+struct GridInfo {
+    int lw;  // logical index of this workgroup among those taking part
+    int n;   // workgroups taking part
+    int x;   // XCD group: blockIdx.x % kXcd
+};
+// what the barriers need, kept in LDS rather than registers: workgroups
+// taking part in this workgroup's group, groups with at least one
+__shared__ int s_grid_shape[2];
+
+struct LaunchSync {
+    unsigned epoch;  // a number the host never reuses for the workspace, never 0
+    int slot;        // join-word set of this launch, host ring 0, 1, 2, 0, ...
+    int join_ticks;  // longest wait for the launched workgroups to join
+};
+
+// Start-up: join, then the leader zeroes the control block (but the join
+// words and the published epoch) and the caller's accumulated outputs,
+// records the groups' sizes and publishes the epoch; the others wait for it
+// before touching any of them.  Returns false in a workgroup that does not
+// take part: it must return at once.  Logical indices are consecutive within
+// an XCD group, so contiguous ranges of pixels or tiles stay in one L2.
+__device__ bool launch_start(int32_t *ctl, const LaunchSync &ls, GridInfo &gi, int32_t *z1, int n1,
+                             int32_t *z2, int n2, int32_t *z3, int n3) {
+    __shared__ int s_role;  // 1 leader, 0 taking part, -1 not taking part
+    __shared__ int s_ticket;
+    __shared__ int s_ok;    // 0 after a (never expected) start-up timeout
+    __shared__ int s_nx[kXcd];
+    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+    const int x = (int)(blockIdx.x % kXcd);
+    const int slot = ls.slot, next = (ls.slot + 1) % kLaunchSlots;
+    if (tid == 0) {
+        unsigned *tk = reinterpret_cast<unsigned *>(&ctl[xw(x, XF_TICKET + slot)]);
+        const unsigned t = __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int role = 0;
+        if (t & kClosed) {
+            role = -1;
+        } else if (t == 0u) {
+            unsigned *lead = reinterpret_cast<unsigned *>(&ctl[G_LEAD + slot]);
+            if (__hip_atomic_fetch_add(lead, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                role = 1;
+        }
+        s_role = role;
+        s_ok = 1;
+        s_ticket = (int)(t & (kClosed - 1u));
+    }
+    __syncthreads();
+    if (s_role < 0) return false;
+    if (s_role == 1) {
+        if (tid == 0) {
+            const long long t0 = wall_clock64();
+            for (;;) {
+                unsigned joined = 0;
+#pragma unroll
+                for (int y = 0; y < kXcd; ++y)
+                    joined += __hip_atomic_load(reinterpret_cast<unsigned *>(&ctl[xw(y, XF_TICKET + slot)]),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                              (kClosed - 1u);
+                if (joined >= gridDim.x || wall_clock64() - t0 > (long long)ls.join_ticks) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+#pragma unroll
+            for (int y = 0; y < kXcd; ++y)
+                s_nx[y] = (int)(__hip_atomic_fetch_or(reinterpret_cast<unsigned *>(&ctl[xw(y, XF_TICKET + slot)]),
+                                                      kClosed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                                (kClosed - 1u));
+        }
+        for (int i = tid; i < kCtlWords; i += nt) {
+            const int f = i % kXStride;
+            const bool join_word = (i < kXcd * kXStride && f >= XF_TICKET && f < XF_TICKET + kLaunchSlots) ||
+                                   (i >= G_LEAD && i < G_LEAD + kLaunchSlots);
+            if (i != G_READY && !join_word && (i < G_NX || i >= G_NX + kXcd)) ctl[i] = 0;
+        }
+        for (int i = tid; i < n1; i += nt) z1[i] = 0;
+        for (int i = tid; i < n2; i += nt) z2[i] = 0;
+        for (int i = tid; i < n3; i += nt) z3[i] = 0;
+        __syncthreads();
+        if (tid < kXcd) {
+            ctl[xw(tid, XF_TICKET + next)] = 0;
+            ctl[G_NX + tid] = s_nx[tid];
+        }
+        if (tid == 0) ctl[G_LEAD + next] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&ctl[G_READY], (int32_t)ls.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (tid == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(&ctl[G_READY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (int32_t)ls.epoch) {
+            if (++spins == kSpinLimit) {  // never expected: leave (the barriers then time out)
+                s_ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+        for (int y = 0; y < kXcd; ++y) s_nx[y] = __hip_atomic_load(&ctl[G_NX + y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!s_ok) return false;
+    int n = 0, off = 0, groups = 0;
+#pragma unroll
+    for (int y = 0; y < kXcd; ++y) {
+        if (y < x) off += s_nx[y];
+        n += s_nx[y];
+        groups += s_nx[y] > 0 ? 1 : 0;
+    }
+    gi.lw = __builtin_amdgcn_readfirstlane(off + s_ticket);  // uniform: scalar registers
+    gi.n = __builtin_amdgcn_readfirstlane(n);
+    gi.x = x;
+    if (tid == 0) {
+        s_grid_shape[0] = s_nx[x];
+        s_grid_shape[1] = groups;
+    }
+    __syncthreads();
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// grid barrier over the workgroups taking part.  Arrivals are counted per XCD
+// group first, then per group, so no counter sees more than
+// max(n / 8, 8) serialised atomics.  Waves of a workgroup share the
 // CU's path to L2, so a workgroup-scope release plus one agent-scope release
 // (L2 write-back) by thread 0 publishes the workgroup's stores; waiting is a
 // relaxed spin (an acquire load would invalidate the caches on every
 // iteration) followed by one acquire.
 
-__device__ void grid_sync(int32_t *ctl, unsigned nblocks) {
+__device__ void grid_sync(int32_t *ctl, const GridInfo &gi) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned x = blockIdx.x % kXcd;
-        const unsigned per_group = nblocks / kXcd;  // nblocks is a multiple of kXcd
+        const unsigned x = (unsigned)gi.x;
+        const unsigned per_group = (unsigned)s_grid_shape[0];
+        const unsigned groups = (unsigned)s_grid_shape[1];
         unsigned *gen = (unsigned *)&ctl[G_GEN];
         unsigned *top = (unsigned *)&ctl[G_TOP];
         unsigned *grp = (unsigned *)&ctl[xw((int)x, XF_BAR)];
@@ -254,7 +391,7 @@ __device__ void grid_sync(int32_t *ctl, unsigned nblocks) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             const unsigned b =
                 __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = (b == kXcd - 1);
+            last = (b == groups - 1);
         }
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -285,15 +422,16 @@ struct SyncSum {
     unsigned flags;
 };
 
-__device__ SyncSum grid_sync_sum(int32_t *ctl, unsigned nblocks, unsigned a, bool flag) {
+__device__ SyncSum grid_sync_sum(int32_t *ctl, const GridInfo &gi, unsigned a, bool flag) {
     __shared__ unsigned long long s_word;
     typedef unsigned long long u64;
     constexpr u64 kLow48 = (1ull << 48) - 1ull;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned x = blockIdx.x % kXcd;
-        const unsigned per_group = nblocks / kXcd;  // nblocks is a multiple of kXcd
+        const unsigned x = (unsigned)gi.x;
+        const u64 per_group = (u64)s_grid_shape[0];
+        const u64 groups = (u64)s_grid_shape[1];
         u64 *gen = reinterpret_cast<u64 *>(&ctl[G_GEN2]);
         u64 *top = reinterpret_cast<u64 *>(&ctl[G_TOP2]);
         u64 *grp = reinterpret_cast<u64 *>(&ctl[xw((int)x, XF_SUM)]);
@@ -309,7 +447,7 @@ __device__ SyncSum grid_sync_sum(int32_t *ctl, unsigned nblocks, unsigned a, boo
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             const u64 tadd = (1ull << 48) | gsum;
             const u64 tprior = __hip_atomic_fetch_add(top, tadd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((tprior >> 48) == kXcd - 1) {
+            if ((tprior >> 48) == groups - 1) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(top, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 word = (((g + 1ull) & 0xffffull) << 48) | ((tprior + tadd) & kLow48);
@@ -338,40 +476,6 @@ __device__ SyncSum grid_sync_sum(int32_t *ctl, unsigned nblocks, unsigned a, boo
     return SyncSum{(unsigned)(w & 0xffffffffull), (unsigned)((w >> 32) & 0xffffull)};
 }
 
-// Launch start-up: logical workgroup 0 zeroes the control block and the
-// caller's accumulated outputs, then publishes this launch's epoch (a number
-// the host never reuses for the workspace); every other workgroup waits for
-// it before touching any of them.  This replaces a separate clearing kernel,
-// whose dispatch gap before a cooperative launch costs more than the wait.
-__device__ void launch_start(int32_t *ctl, unsigned epoch, int32_t *z1, int n1, int32_t *z2, int n2,
-                             int32_t *z3, int n3) {
-    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
-    const int n = (int)gridDim.x, b = (int)blockIdx.x;
-    const bool first = (b % kXcd) * (n / kXcd) + b / kXcd == 0;  // logical workgroup 0
-    if (first) {
-        for (int i = tid; i < kCtlWords; i += nt)
-            if (i != G_READY) ctl[i] = 0;
-        for (int i = tid; i < n1; i += nt) z1[i] = 0;
-        for (int i = tid; i < n2; i += nt) z2[i] = 0;
-        for (int i = tid; i < n3; i += nt) z3[i] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_store(&ctl[G_READY], (int32_t)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        if (tid == 0) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&ctl[G_READY], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-                   (int32_t)epoch) {
-                if (++spins == kSpinLimit) break;  // the timeout flag cannot be trusted yet
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-    }
-    __syncthreads();
-}
-
 __device__ inline int ld_ctl(const int32_t *ctl, int i) {
     return __hip_atomic_load(&ctl[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -388,14 +492,6 @@ __device__ inline int max_x(const int32_t *ctl, int field) {
 #pragma unroll
     for (int x = 0; x < kXcd; ++x) s = max(s, ld_ctl(ctl, xw(x, field)));
     return s;
-}
-
-// logical workgroup id: consecutive logical ids share an XCD, so contiguous
-// ranges of pixels / list entries stay in one L2
-__device__ inline int logical_block() {
-    int n = (int)gridDim.x;
-    int b = (int)blockIdx.x;
-    return (b % kXcd) * (n / kXcd) + b / kXcd;
 }
 
 // ball offsets {(n, m): 0 < n^2 + m^2 <= eps^2}, m ascending then n, and the

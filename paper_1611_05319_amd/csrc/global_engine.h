@@ -1,4 +1,4 @@
-// Global-front engine: one cooperative persistent launch, a grid barrier
+// Global-front engine: one persistent launch, a grid barrier
 // between shells, the front kept as a global list (tracked form) or found by
 // one lane per pixel per shell (untracked form); Guidefill, arXiv 1611.05319,
 // Algorithm 1 and Sec. 3.5.  Also the reverse-shell adjoint over a recorded
@@ -33,7 +33,7 @@ struct FillArgs {
     double a;  // mu^2 / (2 eps^2)
     double c;  // < 0 onion
     int ghost;
-    unsigned epoch;  // launch start-up handshake
+    LaunchSync sync;  // launch start-up (join words and epoch)
 };
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
@@ -134,11 +134,11 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
     __shared__ int s_frame_hole[kFrameCap];
 
     const int tid = threadIdx.x;
-    const int nblk = (int)gridDim.x;
-    const int lw = logical_block();
-    const int xcd = (int)(blockIdx.x % kXcd);
-    launch_start(A.ctl, A.epoch, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
-                 A.shell_off, A.shell_off ? 1 : 0);
+    GridInfo grid;
+    if (!launch_start(A.ctl, A.sync, grid, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
+                      A.shell_off, A.shell_off ? 1 : 0))
+        return;  // joined after the poll closed
+    const int nblk = grid.n, lw = grid.lw, xcd = grid.x;
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     if (tid == 0) s_list_n = s_ord_n = s_fill_n = s_active_n = s_hole_n = s_err_n = 0;
     for (int i = tid; i < kFrameCap; i += kBlock) {
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
             if (s_frame_hole[i]) atomicAdd(&A.stats[8 + 4 * i + 2], s_frame_hole[i]);
     }
     GF_TACC(0);
-    grid_sync(ctl, (unsigned)nblk);
+    grid_sync(ctl, grid);
     GF_TACC(3);
 
     // ---- shells -------------------------------------------------------------
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
         // the barrier carries what every workgroup needs next: the length of the
         // next front (tracked) or this shell's fills (untracked), and whether any
         // workgroup filled a pixel
-        const SyncSum ss = grid_sync_sum(ctl, (unsigned)nblk, (unsigned)(track ? appended : wg_fill),
+        const SyncSum ss = grid_sync_sum(ctl, grid, (unsigned)(track ? appended : wg_fill),
                                          wg_fill != 0);
         GF_TACC(3);
         GF_TCNT(7, 1);
@@ -386,6 +386,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
         A.stats[4] = sum_x(ctl, XF_ERR);
         A.stats[5] = trunc;
         A.stats[6] = ld_ctl(ctl, G_TIMEOUT);
+        A.stats[7] = nblk;
     }
 }
 
@@ -409,7 +410,7 @@ struct BwdArgs {
     double eps;
     double a;
     int ghost;
-    unsigned epoch;  // launch start-up handshake
+    LaunchSync sync;  // launch start-up (join words and epoch)
 };
 
 // Adjoint of one filled pixel x (shell k), one pass over its ball:
@@ -626,9 +627,9 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
     __shared__ float2 s_gd[kItemCap];
     __shared__ float s_agg[(kBlock / G) * kAggPatch];  // one support patch per group
     const int tid = threadIdx.x;
-    const int nblk = (int)gridDim.x;
-    const int lw = logical_block();
-    launch_start(A.ctl, A.epoch, nullptr, 0, nullptr, 0, nullptr, 0);
+    GridInfo grid;
+    if (!launch_start(A.ctl, A.sync, grid, nullptr, 0, nullptr, 0, nullptr, 0)) return;
+    const int nblk = grid.n, lw = grid.lw;
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     __syncthreads();
     const int T = s_T;
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
             for (long long i = lo * A.C + tid; i < hi * A.C; i += kBlock) A.grad_img[i] = A.grad_out[i];
         for (long long i = lo * 2 + tid; i < hi * 2; i += kBlock) A.grad_guide[i] = 0.0f;
     }
-    grid_sync(A.ctl, (unsigned)nblk);
+    grid_sync(A.ctl, grid);
     const int nG = kBlock / G;
     const int gi = tid / G, l = tid & (G - 1);
     const int D = (int)ceil(A.eps);
@@ -664,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
                                      use_agg ? s_agg + gi * kAggPatch : nullptr, D);
             }
         }
-        grid_sync(A.ctl, (unsigned)nblk);
+        grid_sync(A.ctl, grid);
     }
 }
 

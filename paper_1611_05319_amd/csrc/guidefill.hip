@@ -7,7 +7,8 @@
 //   GF_ENGINE_FRONT   one grid barrier per shell, the front as a global list
 //                     (global_engine.h); also records the fill order the
 //                     adjoint replays.
-// Both run as one cooperative persistent launch; its first workgroup zeroes
+// Both run as one persistent launch (an ordinary grid sized to what the
+// device holds); at start-up the resident workgroups join, one of them zeroes
 // the control words and the stats while the others wait for it.
 //
 // All arithmetic of the fill is FP64: the ghost offsets must be bit-identical
@@ -34,29 +35,16 @@ using namespace gfk;
 
 namespace {
 
-// Launch epochs per workspace: a value the workspace's control block has not
-// held (the kernels' start-up handshake waits for it).  The first epoch of a
-// workspace is drawn from the clock and the address, so stale or arbitrary
-// content is unlikely to match it; it is never 0 (a zeroed workspace).
-unsigned next_epoch(const void *ws) {
-    static std::mutex mu;
-    static std::unordered_map<const void *, unsigned> epochs;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = epochs.find(ws);
-    unsigned e;
-    if (it == epochs.end()) {
-        const unsigned long long t =
-            (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count();
-        const unsigned long long p = (unsigned long long)(uintptr_t)ws;
-        e = (unsigned)((t ^ (t >> 32) ^ (p >> 8) ^ (p >> 40)) * 2654435761u);
-        epochs.emplace(ws, e);
-        it = epochs.find(ws);
-    }
-    e = it->second + 1u;
-    if (e == 0u) e = 1u;
-    it->second = e;
-    return e;
-}
+// Launch start-up per workspace: an epoch the workspace's control block has
+// not held (the kernels' start-up handshake waits for it) and the join-word
+// set of the ring (each launch clears the next set; a zeroed workspace has
+// all of them clear).  The first epoch of a workspace is drawn from the clock
+// and the address, so stale or arbitrary content is unlikely to match it; it
+// is never 0 (a zeroed workspace).  The state advances only once a launch is
+// enqueued (a call that fails before its launch must not skip a set: the
+// set after it would not have been cleared).
+LaunchSync peek_launch(const void *ws);
+void commit_launch(const void *ws, const LaunchSync &ls);
 
 thread_local char g_last_error[512] = "";
 
@@ -78,7 +66,7 @@ int count_offsets(double eps) {
 
 struct DevInfo {
     int cus = 0;
-    bool coop = false;
+    int clock_khz = 100000;    // constant clock (wall_clock64) rate
     size_t lds_block = 65536;  // bytes of LDS one workgroup may use
 };
 
@@ -92,7 +80,8 @@ DevInfo device_info(int dev) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) d.cus = v;
     v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) d.coop = v != 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+        d.clock_khz = v;
     v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
         d.lds_block = (size_t)v;
@@ -104,6 +93,41 @@ DevInfo device_info(int dev) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct LaunchState {
+    unsigned epoch;
+    int slot;
+};
+std::mutex g_launch_mu;
+std::unordered_map<const void *, LaunchState> g_launch_states;
+
+LaunchSync peek_launch(const void *ws) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const int khz = device_info(dev).clock_khz;
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    auto it = g_launch_states.find(ws);
+    if (it == g_launch_states.end()) {
+        const unsigned long long t =
+            (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count();
+        const unsigned long long p = (unsigned long long)(uintptr_t)ws;
+        const unsigned e = (unsigned)((t ^ (t >> 32) ^ (p >> 8) ^ (p >> 40)) * 2654435761u);
+        it = g_launch_states.emplace(ws, LaunchState{e, kLaunchSlots - 1}).first;
+    }
+    LaunchSync ls;
+    ls.epoch = it->second.epoch + 1u;
+    if (ls.epoch == 0u) ls.epoch = 1u;
+    ls.slot = (it->second.slot + 1) % kLaunchSlots;
+    // the launched workgroups normally all join within a few microseconds;
+    // 50 us bounds the wait when some of them cannot be resident
+    ls.join_ticks = (int)std::min<long long>((long long)khz * 50 / 1000, 1 << 30);
+    return ls;
+}
+
+void commit_launch(const void *ws, const LaunchSync &ls) {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    g_launch_states[ws] = LaunchState{ls.epoch, ls.slot};
+}
 
 gf_status validate(const gf_params *p, int B, int H, int W, int C, gf_dtype dt) {
     if (!p) return GF_EINVAL;
@@ -207,16 +231,19 @@ int cached_occupancy(int dev, const void *fn, int block, size_t dyn_lds, hipErro
     return occ;
 }
 
+// One persistent launch: an ordinary grid of per_cu workgroups per compute
+// unit (at most what the occupancy allows, a multiple of the XCD count); the
+// kernels' start-up finds which of them are resident.
 template <typename K>
-gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long long max_blocks,
-                      size_t dyn_lds, hipStream_t stream, int block = kBlock) {
+gf_status launch_persistent(K kernel, const void *args_ptr, int blocks_per_cu, long long max_blocks,
+                            size_t dyn_lds, hipStream_t stream, int block = kBlock) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) { set_err("hipGetDevice", e); return GF_EDEVICE; }
     DevInfo di = device_info(dev);
-    if (!di.coop || di.cus <= 0) {
-        snprintf(g_last_error, sizeof g_last_error, "device %d has no cooperative launch", dev);
-        return GF_EUNSUPPORTED;
+    if (di.cus <= 0) {
+        snprintf(g_last_error, sizeof g_last_error, "device %d reports no compute units", dev);
+        return GF_EDEVICE;
     }
     e = hipSuccess;
     const int occ = cached_occupancy(dev, reinterpret_cast<const void *>(kernel), block, dyn_lds, &e);
@@ -233,9 +260,9 @@ gf_status launch_coop(K kernel, const void *args_ptr, int blocks_per_cu, long lo
     grid = (grid / kXcd) * kXcd;
     if (grid < kXcd) grid = kXcd;
     void *kargs[] = {const_cast<void *>(args_ptr)};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3((unsigned)grid),
-                                   dim3(block), kargs, dyn_lds, stream);
-    if (e != hipSuccess) { set_err("hipLaunchCooperativeKernel", e); return GF_EDEVICE; }
+    e = hipLaunchKernel(reinterpret_cast<const void *>(kernel), dim3((unsigned)grid), dim3(block), kargs,
+                        dyn_lds, stream);
+    if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
     return GF_OK;
 }
 
@@ -243,10 +270,10 @@ template <typename TS>
 gf_status run_front(const FillArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
     if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers allow
-    if (G == 8) return launch_coop(fill_kernel<TS, 8>, &A, bpc, mb, 0, s);
-    if (G == 16) return launch_coop(fill_kernel<TS, 16>, &A, bpc, mb, 0, s);
-    if (G == 32) return launch_coop(fill_kernel<TS, 32>, &A, bpc, mb, 0, s);
-    return launch_coop(fill_kernel<TS, 64>, &A, bpc, mb, 0, s);
+    if (G == 8) return launch_persistent(fill_kernel<TS, 8>, &A, bpc, mb, 0, s);
+    if (G == 16) return launch_persistent(fill_kernel<TS, 16>, &A, bpc, mb, 0, s);
+    if (G == 32) return launch_persistent(fill_kernel<TS, 32>, &A, bpc, mb, 0, s);
+    return launch_persistent(fill_kernel<TS, 64>, &A, bpc, mb, 0, s);
 }
 
 // threads per tile workgroup
@@ -256,11 +283,11 @@ template <typename TS, int NT>
 gf_status run_tiled_nt(const TileArgs &A, int G, int bpc, size_t lds, hipStream_t s) {
     const long long mb = 1ll << 30;
     if (bpc == 0) bpc = 8;  // as many workgroups per CU as the LDS and registers allow
-    if (G == 4) return launch_coop(tile_kernel<TS, 4, NT>, &A, bpc, mb, lds, s, NT);
-    if (G == 8) return launch_coop(tile_kernel<TS, 8, NT>, &A, bpc, mb, lds, s, NT);
-    if (G == 16) return launch_coop(tile_kernel<TS, 16, NT>, &A, bpc, mb, lds, s, NT);
-    if (G == 32) return launch_coop(tile_kernel<TS, 32, NT>, &A, bpc, mb, lds, s, NT);
-    return launch_coop(tile_kernel<TS, 64, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 4) return launch_persistent(tile_kernel<TS, 4, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 8) return launch_persistent(tile_kernel<TS, 8, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 16) return launch_persistent(tile_kernel<TS, 16, NT>, &A, bpc, mb, lds, s, NT);
+    if (G == 32) return launch_persistent(tile_kernel<TS, 32, NT>, &A, bpc, mb, lds, s, NT);
+    return launch_persistent(tile_kernel<TS, 64, NT>, &A, bpc, mb, lds, s, NT);
 }
 
 template <typename TS>
@@ -274,10 +301,10 @@ gf_status run_tiled(const TileArgs &A, int G, int NT, int bpc, size_t lds, hipSt
 template <typename TS>
 gf_status run_bwd(const BwdArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
-    if (G == 8) return launch_coop(bwd_kernel<TS, 8>, &A, bpc, mb, 0, s);
-    if (G == 16) return launch_coop(bwd_kernel<TS, 16>, &A, bpc, mb, 0, s);
-    if (G == 32) return launch_coop(bwd_kernel<TS, 32>, &A, bpc, mb, 0, s);
-    return launch_coop(bwd_kernel<TS, 64>, &A, bpc, mb, 0, s);
+    if (G == 8) return launch_persistent(bwd_kernel<TS, 8>, &A, bpc, mb, 0, s);
+    if (G == 16) return launch_persistent(bwd_kernel<TS, 16>, &A, bpc, mb, 0, s);
+    if (G == 32) return launch_persistent(bwd_kernel<TS, 32>, &A, bpc, mb, 0, s);
+    return launch_persistent(bwd_kernel<TS, 64>, &A, bpc, mb, 0, s);
 }
 
 struct WsLayout {
@@ -382,7 +409,7 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     char *ws = reinterpret_cast<char *>(workspace);
     int32_t *ctl = reinterpret_cast<int32_t *>(ws + L.ctl);
     const double a = p->mu * p->mu / (2.0 * p->eps * p->eps);
-    const unsigned epoch = next_epoch(workspace);
+    const LaunchSync ls = peek_launch(workspace);
     if (p->engine == GF_ENGINE_FRONT) {
         FillArgs A;
         A.in = img_in;
@@ -411,9 +438,11 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
         A.a = a;
         A.c = p->c;
         A.ghost = p->ghost ? 1 : 0;
-        A.epoch = epoch;
-        if (dt == GF_F32) return run_front<float>(A, G, p->blocks_per_cu, s);
-        return run_front<__half>(A, G, p->blocks_per_cu, s);
+        A.sync = ls;
+        const gf_status rc = dt == GF_F32 ? run_front<float>(A, G, p->blocks_per_cu, s)
+                                          : run_front<__half>(A, G, p->blocks_per_cu, s);
+        if (rc == GF_OK) commit_launch(workspace, ls);
+        return rc;
     }
     TileArgs A;
     A.in = img_in;
@@ -456,10 +485,12 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     A.eps = p->eps;
     A.a = a;
     A.c = p->c;
-    A.epoch = epoch;
+    A.sync = ls;
     const int NT = tile_threads_of(p);
-    if (dt == GF_F32) return run_tiled<float>(A, G, NT, p->blocks_per_cu, geom.lds, s);
-    return run_tiled<__half>(A, G, NT, p->blocks_per_cu, geom.lds, s);
+    const gf_status rc = dt == GF_F32 ? run_tiled<float>(A, G, NT, p->blocks_per_cu, geom.lds, s)
+                                      : run_tiled<__half>(A, G, NT, p->blocks_per_cu, geom.lds, s);
+    if (rc == GF_OK) commit_launch(workspace, ls);
+    return rc;
 }
 
 gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,
@@ -533,9 +564,11 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
     A.eps = p->eps;
     A.a = p->mu * p->mu / (2.0 * p->eps * p->eps);
     A.ghost = p->ghost ? 1 : 0;
-    A.epoch = next_epoch(workspace);
-    if (dt == GF_F32) return run_bwd<float>(A, G, p->blocks_per_cu, s);
-    return run_bwd<__half>(A, G, p->blocks_per_cu, s);
+    A.sync = peek_launch(workspace);
+    const gf_status rc = dt == GF_F32 ? run_bwd<float>(A, G, p->blocks_per_cu, s)
+                                      : run_bwd<__half>(A, G, p->blocks_per_cu, s);
+    if (rc == GF_OK) commit_launch(workspace, A.sync);
+    return rc;
 }
 
 }  // extern "C"

@@ -42,7 +42,7 @@ struct TileArgs {
     int tiles_x, tiles_y, ntiles;
     int max_shells, inplace, ghost, tile_track, local_track;
     double eps, a, c;
-    unsigned epoch;  // launch start-up handshake
+    LaunchSync sync;  // launch start-up (join words and epoch)
 };
 
 
@@ -80,9 +80,6 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     __shared__ int s_seg[kXcd];     // this pass's active-tile list length per XCD
 
     const int tid = threadIdx.x;
-    const int nblk = (int)gridDim.x;
-    const int lw = logical_block();
-    const int xcd = (int)(blockIdx.x % kXcd);
     const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
     const int CP = padded_channels(C);  // channels per window pixel
     int32_t *st = reinterpret_cast<int32_t *>(smem);
@@ -93,8 +90,11 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                                                 align16((size_t)WN * CP * sizeof(TS)) +
                                                 align16((size_t)WN * 8));
     int32_t *ctl = A.ctl;
-    launch_start(ctl, A.epoch, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
-                 nullptr, 0);
+    GridInfo grid;
+    if (!launch_start(ctl, A.sync, grid, A.stats, 8 + 4 * A.B, A.front_hist, A.front_hist ? A.kcap : 0,
+                 nullptr, 0))
+        return;  // joined after the poll closed
+    const int nblk = grid.n, lw = grid.lw, xcd = grid.x;
     build_offsets(A.eps, s_off, s_rinv, &s_T);
     if (tid == 0) {
         s_stage_n = 0;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         if (s_err_n) atomicAdd(&ctl[xw(xcd, XF_ERR)], s_err_n);
     }
     GF_TACC(0);
-    grid_sync(ctl, (unsigned)nblk);
+    grid_sync(ctl, grid);
     GF_TACC(5);
 
     // ---- passes of S shells -------------------------------------------------
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     long long total_filled = 0;
     int max_front = 0;  // kept by thread 0 of logical workgroup 0
     const int nG = NT / G;
-    const int gi = tid / G, l = tid & (G - 1);
+    const int l = tid & (G - 1);
     const int wave_base = tid & ~63;
     for (int p = 0; total_filled < total_hole; ++p) {
         const int k0 = p * A.S;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             atomicMax(&ctl[xw(xcd, XF_KMAX)], s_pass_kmax);
         }
         GF_TACC(9);
-        grid_sync(ctl, (unsigned)nblk);
+        grid_sync(ctl, grid);
         GF_TACC(5);
         GF_TCNT(10, 1);
         const int fills = sum_x(ctl, XF_PFILL + p % 3);
@@ -547,6 +547,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         A.stats[4] = sum_x(ctl, XF_ERR);
         A.stats[5] = 0;
         A.stats[6] = ld_ctl(ctl, G_TIMEOUT);
+        A.stats[7] = nblk;
     }
 }
 

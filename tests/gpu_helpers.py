@@ -47,6 +47,7 @@ def gpu_fill(img, label, guide, **kw):
     s = r.shell.cpu().numpy()
     st = r.host_stats()
     assert not st["sync_timeout"], "a grid barrier gave up waiting"
+    assert st["workgroups"] >= 8, "the persistent launch reported no workgroups"
     if not batched:
         u, s = u[0], s[0]
     return u, s, st, r
