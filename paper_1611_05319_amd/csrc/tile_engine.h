@@ -50,6 +50,7 @@ constexpr int kWinPerThread = 4;     // window pixels staged per thread per roun
 constexpr int kMaxWindow = 8192;     // window pixels (uint16 local lists)
 constexpr int kTileStageCap = 512;   // LDS staging of next-pass tiles per workgroup
 constexpr int kTileStaticLds = 8192; // bytes of static LDS the tile kernel may use
+constexpr int32_t kKnown = 1;        // window staging: readable from the start (not stored)
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
@@ -62,6 +63,62 @@ template <typename TS> __host__ __device__ inline size_t tile_lds_bytes(int WN, 
 
 // NT threads per workgroup: 1024 (one large window per CU) or 256 (several
 // small windows share a CU)
+// Out-of-place copy of the pixels that are not in the hole (label != 1), by
+// this workgroup's share [share, share + 1) of `shares`.  Pixels go in chunks
+// of whole 16-byte lanes (4 binary32 RGB pixels: three lanes): a chunk with no
+// hole pixel is copied lane by lane, the others pixel by pixel.  No pixel it
+// writes is read back by the kernel: windows take the colours of pixels known
+// from the start from the input, so the copy runs beside the first pass's
+// fills.  Falls back to pixel by pixel where the buffers are not aligned.
+template <typename TS>
+__device__ void copy_known(const TS *__restrict__ in, TS *__restrict__ out, const uint8_t *__restrict__ label,
+                           int C, long long NP, int share, int shares) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int bpp = C * (int)sizeof(TS);                   // 2 .. 16 bytes per pixel
+    const int g = (bpp & 15) == 0 ? 16 : (bpp & 7) == 0 ? 8 : (bpp & 3) == 0 ? 4 : 2;  // gcd(bpp, 16)
+    const int ppc = 16 / g, lanes = bpp / g;                // pixels and 16-byte lanes per chunk
+    const bool vec = ((((uintptr_t)in | (uintptr_t)out) & 15) == 0) && (((uintptr_t)label & (ppc - 1)) == 0);
+    const long long nch = vec ? NP / ppc : 0;
+    const long long c0 = nch * share / shares, c1 = nch * (share + 1) / shares;
+    for (long long c = c0 + tid; c < c1; c += nt) {
+        const long long p0 = c * ppc;
+        uint32_t lo = 0, hi = 0;  // the chunk's labels, one byte each
+        if (ppc == 8) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(label + p0);
+            lo = v.x;
+            hi = v.y;
+        } else if (ppc == 4) {
+            lo = *reinterpret_cast<const uint32_t *>(label + p0);
+        } else if (ppc == 2) {
+            lo = *reinterpret_cast<const uint16_t *>(label + p0);
+        } else {
+            lo = label[p0];
+        }
+        // a byte equal to 1 marks a hole pixel; bytes past ppc are 0
+        const uint32_t xl = lo ^ 0x01010101u, xh = hi ^ 0x01010101u;
+        const uint32_t ml = ppc >= 4 ? 0xffffffffu : (ppc == 2 ? 0xffffu : 0xffu);
+        const uint32_t zl = ((xl - 0x01010101u) & ~xl & 0x80808080u) & (ml & 0x80808080u);
+        const uint32_t zh = ppc == 8 ? ((xh - 0x01010101u) & ~xh & 0x80808080u) : 0u;
+        const uint4 *src = reinterpret_cast<const uint4 *>(in) + c * lanes;
+        uint4 *dst = reinterpret_cast<uint4 *>(out) + c * lanes;
+        if ((zl | zh) == 0u) {
+            for (int u = 0; u < lanes; ++u) dst[u] = src[u];
+        } else {
+            for (int j = 0; j < ppc; ++j) {
+                const uint32_t b = ((j < 4 ? lo >> (8 * j) : hi >> (8 * (j - 4)))) & 0xffu;
+                if (b == 1u) continue;
+                for (int ch = 0; ch < C; ++ch) out[(p0 + j) * C + ch] = in[(p0 + j) * C + ch];
+            }
+        }
+    }
+    // the pixels past the whole chunks (all of them without alignment)
+    const long long rest0 = nch * ppc, nrest = NP - rest0;
+    const long long r0 = rest0 + nrest * share / shares, r1 = rest0 + nrest * (share + 1) / shares;
+    for (long long p = r0 + tid; p < r1; p += nt)
+        if (label[p] != 1)
+            for (int ch = 0; ch < C; ++ch) out[p * C + ch] = in[p * C + ch];
+}
+
 template <typename TS, int G, int NT>
 __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -111,13 +168,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     GF_RT_DECL(rt_fill);
     GF_RT_DECL(rt_sync);
 
-    // ---- phase A: copy, shell codes, per-tile hole counts, pass-0 tiles ----
-    if (!A.inplace) {
-        const size_t esz = sizeof(TS) * (size_t)C;
-        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
-        copy_range(reinterpret_cast<const char *>(A.in), reinterpret_cast<char *>(A.out),
-                   (size_t)lo * esz, (size_t)hi * esz);
-    }
+    // ---- phase A: shell codes, per-tile hole counts, pass-0 tiles ----------
+    // (the out-of-place copy of known pixels waits for the first pass)
+    bool copied = A.inplace != 0;
     {
         const int tpx = A.TW * A.TH;
         int nb = (kWinPerThread * NT) / tpx;  // tiles per batch: <= kWinPerThread labels per thread
@@ -230,10 +283,13 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             const int ox0 = tx * A.TW - A.Hh, oy0 = ty * A.TH - A.Hh;
             const int32_t *S = A.shell + (long long)f * A.HW;
             const TS *U = reinterpret_cast<const TS *>(A.out) + (long long)f * A.HW * C;
+            const TS *Ui = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
             const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
             // 1. stage the window in two round trips: states (readable before the
             //    pass / bystander / hole; pixels filled by neighbours during this pass
-            //    count as hole), then colours of readable and guides of hole pixels
+            //    count as hole), then colours of readable pixels (from the input for
+            //    pixels known from the start, else from the output) and guides of
+            //    hole pixels
             for (int base = 0; base < WN; base += kWinPerThread * NT) {
                 int32_t code[kWinPerThread];
 #pragma unroll
@@ -245,7 +301,8 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         const int x = ox0 + wx, y = oy0 + wy;
                         if (x >= 0 && x < W && y >= 0 && y < H) {
                             const int32_t s = S[y * W + x];
-                            code[r] = (s == -1 || (s >= 0 && s < k0)) ? S_READABLE
+                            code[r] = s == -1                    ? kKnown
+                                      : (s >= 0 && s < k0)         ? S_READABLE
                                       : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
                         }
                     }
@@ -254,11 +311,13 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                 for (int r = 0; r < kWinPerThread; ++r) {
                     const int i = base + tid + r * NT;
                     if (i < WN) {
-                        st[i] = code[r];
+                        const bool known = code[r] == kKnown;
+                        st[i] = known ? S_READABLE : code[r];
                         const int wy = i / WW, wx = i - wy * WW;
                         const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
-                        if (code[r] == S_READABLE) {
-                            for (int ch = 0; ch < C; ++ch) col[i * CP + ch] = U[q * C + ch];
+                        if (known || code[r] == S_READABLE) {
+                            const TS *src = known ? Ui : U;
+                            for (int ch = 0; ch < C; ++ch) col[i * CP + ch] = src[q * C + ch];
                         } else if (code[r] == S_HOLE) {
                             gd[i] = Gd[q];
                         }
@@ -483,6 +542,18 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             }
             GF_TACC(4);
         }
+        if (!copied) {  // first pass: copy the known pixels, by the workgroups
+            const int idle = nblk - n_tiles_pass;  // without a tile if there are enough
+            if (idle > 0 && idle >= nblk / 4) {
+                if (lw >= n_tiles_pass)
+                    copy_known<TS>(reinterpret_cast<const TS *>(A.in), reinterpret_cast<TS *>(A.out), A.label, C,
+                                   A.NP, lw - n_tiles_pass, idle);
+            } else {
+                copy_known<TS>(reinterpret_cast<const TS *>(A.in), reinterpret_cast<TS *>(A.out), A.label, C, A.NP,
+                               lw, nblk);
+            }
+            copied = true;
+        }
         stage_flush(stage, nxt_act, nxt_cnt, &s_base);
         if (tid == 0 && s_pass_fill) {
             atomicAdd(&ctl[xw(xcd, XF_PFILL + p % 3)], s_pass_fill);
@@ -507,7 +578,10 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     // ---- finish ---------------------------------------------------------------
     GF_RT_FLUSH(11, rt_fill);
     GF_RT_FLUSH(13, rt_sync);
-    if (total_filled < total_hole) {  // leftovers never became ready: shell -3
+    if (!copied)  // no pass ran (no hole pixel)
+        copy_known<TS>(reinterpret_cast<const TS *>(A.in), reinterpret_cast<TS *>(A.out), A.label, C, A.NP, lw,
+                       nblk);
+    if (total_filled < total_hole) {  // leftovers never became ready: shell -3, input colour
         for (int t = lw; t < A.ntiles; t += nblk) {
             if (A.t_rem[t] == 0) continue;
             const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
@@ -515,7 +589,14 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             int32_t *Sw = A.shell + (long long)f * A.HW;
             for (int i = tid; i < tw * th; i += NT) {
                 const int y = ty * A.TH + i / tw, x = tx * A.TW + i % tw;
-                if (Sw[y * W + x] == S_HOLE) Sw[y * W + x] = S_UNFILLED;
+                if (Sw[y * W + x] == S_HOLE) {
+                    Sw[y * W + x] = S_UNFILLED;
+                    if (!A.inplace) {
+                        const long long q = ((long long)f * A.HW + (long long)y * W + x) * C;
+                        for (int ch = 0; ch < C; ++ch)
+                            reinterpret_cast<TS *>(A.out)[q + ch] = reinterpret_cast<const TS *>(A.in)[q + ch];
+                    }
+                }
             }
         }
     }
