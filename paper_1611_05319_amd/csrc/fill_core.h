@@ -39,36 +39,21 @@ template <typename TS> struct GlobalView {
     }
 };
 
-// channels of a pixel in an LDS window: 3 are padded to 4 for vector loads
-__host__ __device__ inline int padded_channels(int C) { return C == 3 ? 4 : C; }
+// channels of a pixel in an LDS window: always 4 (padding never read into a
+// result), so a pixel's colours are one vector load
+__host__ __device__ inline int padded_channels(int) { return 4; }
 
-template <typename TS> __device__ inline void lds_colours(const TS *p, int CP, float o[4]);
-template <> __device__ inline void lds_colours<float>(const float *p, int CP, float o[4]) {
-    if (CP == 4) {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
-        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-    } else if (CP == 2) {
-        const float2 v = *reinterpret_cast<const float2 *>(p);
-        o[0] = v.x; o[1] = v.y; o[2] = 0.0f; o[3] = 0.0f;
-    } else {
-        o[0] = p[0]; o[1] = 0.0f; o[2] = 0.0f; o[3] = 0.0f;
-    }
+template <typename TS> __device__ inline void lds_colours(const TS *p, float o[4]);
+template <> __device__ inline void lds_colours<float>(const float *p, float o[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(__builtin_assume_aligned(p, 16));
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
-template <> __device__ inline void lds_colours<__half>(const __half *p, int CP, float o[4]) {
-    if (CP == 4) {
-        const uint2 v = *reinterpret_cast<const uint2 *>(p);
-        o[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
-        o[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
-        o[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
-        o[3] = __half2float(__ushort_as_half((unsigned short)(v.y >> 16)));
-    } else if (CP == 2) {
-        const unsigned v = *reinterpret_cast<const unsigned *>(p);
-        o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
-        o[1] = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
-        o[2] = 0.0f; o[3] = 0.0f;
-    } else {
-        o[0] = __half2float(p[0]); o[1] = 0.0f; o[2] = 0.0f; o[3] = 0.0f;
-    }
+template <> __device__ inline void lds_colours<__half>(const __half *p, float o[4]) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(__builtin_assume_aligned(p, 8));
+    o[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
+    o[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
+    o[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
+    o[3] = __half2float(__ushort_as_half((unsigned short)(v.y >> 16)));
 }
 
 // tile window in LDS (state = window codes; pixels outside the frame are
@@ -83,7 +68,7 @@ template <typename TS> struct LdsView {
     __device__ int index(int x, int y) const { return y * WW + x; }
     __device__ int pitch() const { return WW; }
     __device__ int32_t state_at(int i) const { return st[i]; }
-    __device__ void colours(int i, float o[4]) const { lds_colours<TS>(col + i * CP, CP, o); }
+    __device__ void colours(int i, float o[4]) const { lds_colours<TS>(col + i * 4, o); }
 };
 
 // Weights are exp(-(q - q_min)) / |(n, m)|: relative to the largest readable
@@ -228,9 +213,11 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
             v.colours(i01, c01);
             v.colours(i11, c11);
             const float fx = fxs[r], fy = fys[r];
+            // channels past C carry padding or zeros: their sums are never used,
+            // so three are interpolated without a test
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
-                if (ch < C) {
+                if (ch < 3 || C == 4) {
                     const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
                     const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
                     const float val = fmaf(fy, bot - top, top);

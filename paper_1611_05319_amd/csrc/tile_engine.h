@@ -317,7 +317,8 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
                         if (known || code[r] == S_READABLE) {
                             const TS *src = known ? Ui : U;
-                            for (int ch = 0; ch < C; ++ch) col[i * CP + ch] = src[q * C + ch];
+#pragma unroll
+                            for (int ch = 0; ch < 4; ++ch) col[i * CP + ch] = ch < C ? src[q * C + ch] : TS(0.0f);
                         } else if (code[r] == S_HOLE) {
                             gd[i] = Gd[q];
                         }
@@ -382,7 +383,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     if (l == 0) {
                         interior = X >= A.Hh && X < A.Hh + A.TW && Y >= A.Hh && Y < A.Hh + A.TH;
                         if (ok) {
-                            for (int ch = 0; ch < C; ++ch) col[wi * CP + ch] = to_storage<TS>(val[ch]);
+#pragma unroll
+                            for (int ch = 0; ch < 4; ++ch)
+                                col[wi * CP + ch] = ch < C ? to_storage<TS>(val[ch]) : TS(0.0f);
                             st[wi] = j;
                             filled_here = true;
                         }
