@@ -121,22 +121,23 @@ def launch_fields(p):
 
 
 def time_steps(fn, steps, warmup, torch):
-    """Warm up, then time exactly `steps` calls: wall clock between two device
-    synchronisations, and per-call HIP events on the current stream."""
+    """Warm up, then time exactly `steps` calls back to back: wall clock
+    between two device synchronisations, and one pair of HIP events on the
+    current stream around the same calls (their time per call: the average
+    launch duration plus the dispatch gap between launches, ~1 us; an event
+    pair around every call would add ~8 us per call to the region)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for a, b in evs:
-        a.record()
+    a.record()
+    for _ in range(steps):
         fn()
-        b.record()
+    b.record()
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / steps
-    ev_ms = [a.elapsed_time(b) for a, b in evs]
-    return wall_ms, float(np.mean(ev_ms)), float(np.median(ev_ms))
+    return wall_ms, a.elapsed_time(b) / steps
 
 
 def main():
@@ -190,12 +191,12 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        wall, ev_mean, ev_med = time_steps(plan.run, args.steps, args.warmup, torch)
+        wall, ev_mean = time_steps(plan.run, args.steps, args.warmup, torch)
         print(json.dumps({"profile": True, "steps": args.steps, "fill_event_ms": ev_mean,
                           "copy_bytes": nb, "K": st["K"], "filled": n_filled}), flush=True)
         return
 
-    wall, ev_mean, ev_med = time_steps(plan.run, args.steps, args.warmup, torch)
+    wall, ev_mean = time_steps(plan.run, args.steps, args.warmup, torch)
     mpix = n_filled / (wall * 1e-3) / 1e6
     nbytes = algorithmic_bytes(B, H, W, C, 4, st["hole"])
     achieved = nbytes / (ev_mean * 1e-3) / 1e9
@@ -222,8 +223,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": recorded_traffic(params, H, W, C),
-                     "algorithmic_bytes": nbytes, "event_ms_mean": round(ev_mean, 5),
-                     "event_ms_median": round(ev_med, 5),
+                     "algorithmic_bytes": nbytes, "event_ms_per_launch": round(ev_mean, 5),
                      "us_per_shell": round(ev_mean * 1e3 / max(st["K"], 1), 3)},
         "cpu_baseline": base,
     }
@@ -231,7 +231,7 @@ def main():
     if extras:
         # tracked vs untracked (one lane per pixel per shell)
         plan_u = gf.FillPlan(img, lab, gd, gf.Params(eps=w2.eps, mu=w2.mu, tracking=False))
-        wall_u, ev_u, _ = time_steps(plan_u.run, args.steps, args.warmup, torch)
+        wall_u, ev_u = time_steps(plan_u.run, args.steps, args.warmup, torch)
         out["untracked"] = {"ms_per_step": round(wall_u, 5), "event_ms": round(ev_u, 5),
                             "value": round(n_filled / (wall_u * 1e-3) / 1e6, 3),
                             "tracked_speedup": round(wall_u / wall, 3)}
@@ -253,8 +253,8 @@ def main():
                 pl.run()
 
         steps4 = max(3, args.steps // 10)
-        wall_b, ev_b, _ = time_steps(plan_b.run, steps4, 2, torch)
-        wall_s, ev_s, _ = time_steps(run_singles, steps4, 1, torch)
+        wall_b, ev_b = time_steps(plan_b.run, steps4, 2, torch)
+        wall_s, ev_s = time_steps(run_singles, steps4, 1, torch)
         nb4 = algorithmic_bytes(*i4.shape, 2, st4["hole"])
         out["batched"] = {"workload": "64 x 1920x1080 RGB fp16 storage, lognormal hole fraction "
                                       "(median 2%), eps=3, mu=50",
@@ -285,8 +285,8 @@ def main():
             bw.run()
 
         steps5 = max(5, args.steps // 5)
-        wall_f, _, _ = time_steps(plan_f.run, steps5, 2, torch)
-        wall_fb, _, _ = time_steps(fwd_bwd, steps5, 2, torch)
+        wall_f, _ = time_steps(plan_f.run, steps5, 2, torch)
+        wall_fb, _ = time_steps(fwd_bwd, steps5, 2, torch)
         out["fwd_bwd"] = {"workload": "16 x 512x512 RGB fp32, band masks 6-16 px, smooth angle "
                                       "field, eps=3, mu=50",
                           "fwd_ms": round(wall_f, 4), "fwd_bwd_ms": round(wall_fb, 4),

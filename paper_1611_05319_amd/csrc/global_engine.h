@@ -162,39 +162,122 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                        (size_t)lo * esz, (size_t)hi * esz);
         }
         Stage st{s_list, &s_list_n, kStageCap};
-        for (long long p = lo + tid; p < hi; p += kBlock) {
-            const uint8_t lab = A.label[p];
-            int32_t code;
-            if (lab == 0) {
-                code = S_READABLE;
-            } else if (lab == 1) {
-                code = S_HOLE;
-                const long long f = p / A.HW;
-                const int q = (int)(p - f * A.HW);
-                if (f < kFrameCap) atomicAdd(&s_frame_hole[f], 1);
-                else atomicAdd(&A.stats[8 + 4 * f + 2], 1);
-                atomicAdd(&s_hole_n, 1);
-                if (track) {
-                    const int y = q / W, x = q - y * W;
-                    const uint8_t *L = A.label + f * A.HW;
-                    bool act = false;
+        const uint8_t *__restrict__ Lab = A.label;
+        int32_t *__restrict__ Sh = A.shell;
+        auto code_of = [&](long long p, uint8_t lab) -> int32_t {
+            if (lab == 0) return S_READABLE;
+            if (lab != 1) {
+                if (lab != 2) atomicAdd(&s_err_n, 1);
+                return S_BYSTANDER;
+            }
+            const long long f = p / A.HW;
+            const int q = (int)(p - f * A.HW);
+            if (f < kFrameCap) atomicAdd(&s_frame_hole[f], 1);
+            else atomicAdd(&A.stats[8 + 4 * f + 2], 1);
+            atomicAdd(&s_hole_n, 1);
+            if (!track) return S_HOLE;
+            const int y = q / W, x = q - y * W;
+            const uint8_t *L = Lab + f * A.HW;
+            bool act = false;
 #pragma unroll
-                    for (int d = 0; d < 9; ++d) {
-                        const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
-                        if (d != 4 && xx >= 0 && xx < W && yy >= 0 && yy < H)
-                            act |= (L[yy * W + xx] == 0);
-                    }
-                    if (act) {
-                        code = S_FRONT;
-                        stage_push(st, (int)p, A.listA, &ctl[G_LIST + 0]);
+            for (int d = 0; d < 9; ++d) {
+                const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
+                if (d != 4 && xx >= 0 && xx < W && yy >= 0 && yy < H) act |= (L[yy * W + xx] == 0);
+            }
+            if (!act) return S_HOLE;
+            stage_push(st, (int)p, A.listA, &ctl[G_LIST + 0]);
+            return S_FRONT;
+        };
+        // 16 pixels per thread and step where the label and shell buffers allow
+        // vector accesses and rows hold whole groups (W a multiple of 16): one
+        // label load covers a group; a group with hole pixels finds its shell-0
+        // front from bit masks of the readable pixels in its row segment and the
+        // segments above and below (x - 1 .. x + 16), with no per-pixel loads
+        long long v0 = hi, v1 = hi;
+        if ((((uintptr_t)Lab | (uintptr_t)Sh) & 15) == 0 && (W & 15) == 0) {
+            v0 = (lo + 15) & ~15ll;
+            v1 = hi & ~15ll;
+            if (v0 > v1) v0 = v1 = hi;
+        }
+        for (long long p = lo + tid; p < v0; p += kBlock) Sh[p] = code_of(p, Lab[p]);
+        // readable pixels (label 0) of the 18 pixels x0 - 1 .. x0 + 16 of a row
+        // segment, bit k for pixel x0 - 1 + k
+        auto readable18 = [&](const uint8_t *row, int x0) -> uint32_t {
+            const uint4 v = *reinterpret_cast<const uint4 *>(row);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            uint32_t m = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) m |= (((wd[j >> 2] >> (8 * (j & 3))) & 0xffu) == 0u ? 2u : 0u) << j;
+            if (x0 > 0 && row[-1] == 0) m |= 1u;
+            if (x0 + 16 < W && row[16] == 0) m |= 1u << 17;
+            return m;
+        };
+#pragma unroll 2
+        for (long long g = v0 + 16ll * tid; g < v1; g += 16ll * kBlock) {
+            const uint4 lv = *reinterpret_cast<const uint4 *>(Lab + g);
+            int4 *dst = reinterpret_cast<int4 *>(Sh + g);
+            if ((lv.x | lv.y | lv.z | lv.w) == 0u) {
+                const int4 r = make_int4(S_READABLE, S_READABLE, S_READABLE, S_READABLE);
+                dst[0] = r;
+                dst[1] = r;
+                dst[2] = r;
+                dst[3] = r;
+                continue;
+            }
+            const uint32_t wd[4] = {lv.x, lv.y, lv.z, lv.w};
+            uint32_t hole = 0, err = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t b = (wd[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                hole |= (b == 1u ? 1u : 0u) << j;
+                err |= (b > 2u ? 1u : 0u) << j;
+            }
+            uint32_t front = 0;
+            if (hole) {
+                const long long f = g / A.HW;
+                const int q = (int)(g - f * A.HW);
+                const int y = q / W, x0 = q - y * W;
+                const int nh = __popc(hole);
+                if (f < kFrameCap) atomicAdd(&s_frame_hole[f], nh);
+                else atomicAdd(&A.stats[8 + 4 * f + 2], nh);
+                atomicAdd(&s_hole_n, nh);
+                if (track) {
+                    const uint32_t c = readable18(Lab + g, x0);
+                    const uint32_t u = y > 0 ? readable18(Lab + g - W, x0) : 0u;
+                    const uint32_t d = y + 1 < H ? readable18(Lab + g + W, x0) : 0u;
+                    const uint32_t vert = u | d;  // pixel j: bits j, j + 1, j + 2 above and below
+                    const uint32_t act = vert | (vert >> 1) | (vert >> 2) | c | (c >> 2);
+                    front = hole & act & 0xffffu;
+                    const int nf = __popc(front);
+                    if (nf) {  // one reservation for the group's front pixels
+                        const int slot = atomicAdd(st.n, nf);
+                        const int inl = max(0, min(nf, st.cap - slot));
+                        const int gpos = inl < nf ? atomicAdd(&ctl[G_LIST + 0], nf - inl) : 0;
+                        int j = 0;
+                        for (uint32_t m = front; m; m &= m - 1u, ++j) {
+                            const int px = (int)(g + __ffs(m) - 1);
+                            if (j < inl) st.buf[slot + j] = px;
+                            else A.listA[gpos + (j - inl)] = px;
+                        }
                     }
                 }
-            } else {
-                code = S_BYSTANDER;
-                if (lab != 2) atomicAdd(&s_err_n, 1);
             }
-            A.shell[p] = code;
+            if (err) atomicAdd(&s_err_n, __popc(err));
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                int32_t c4[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int jj = 4 * q4 + j;
+                    const uint32_t b = (wd[q4] >> (8 * j)) & 0xffu;
+                    c4[j] = b == 0u ? S_READABLE
+                            : b == 1u ? (((front >> jj) & 1u) ? S_FRONT : S_HOLE)
+                                      : S_BYSTANDER;
+                }
+                dst[q4] = make_int4(c4[0], c4[1], c4[2], c4[3]);
+            }
         }
+        for (long long p = v1 + tid; p < hi; p += kBlock) Sh[p] = code_of(p, Lab[p]);
         stage_flush(st, A.listA, &ctl[G_LIST + 0], &s_base);
         if (tid == 0) {
             if (s_hole_n) atomicAdd(&ctl[xw(xcd, XF_HOLE)], s_hole_n);
