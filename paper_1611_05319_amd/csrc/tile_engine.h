@@ -135,6 +135,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     __shared__ int s_front_in[32];  // interior active pixels per local shell
     __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
     __shared__ int s_seg[kXcd];     // this pass's active-tile list length per XCD
+    __shared__ int s_pf[kXcd];      // the pass's fills per XCD
 
     const int tid = threadIdx.x;
     const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
@@ -172,12 +173,58 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     // (the out-of-place copy of known pixels waits for the first pass)
     bool copied = A.inplace != 0;
     {
-        const int tpx = A.TW * A.TH;
-        int nb = (kWinPerThread * NT) / tpx;  // tiles per batch: <= kWinPerThread labels per thread
+        // 16-pixel row segments per thread where tiles and rows hold whole
+        // segments and the buffers allow vector accesses (one label load, four
+        // stores), else single pixels, kWinPerThread per thread
+        const bool vec = (A.TW & 15) == 0 && (W & 15) == 0 &&
+                         ((((uintptr_t)A.label | (uintptr_t)A.shell) & 15) == 0);
+        const int segs = A.TW / 16;
+        const int tpx = vec ? segs * A.TH : A.TW * A.TH;  // work items per tile
+        int nb = vec ? NT / tpx : (kWinPerThread * NT) / tpx;  // tiles per batch
         nb = nb < 1 ? 1 : (nb > 16 ? 16 : nb);
         for (int b0 = 0; lw + b0 * nblk < A.ntiles; b0 += nb) {
             if (tid < 16) s_tcnt[tid] = 0;
             __syncthreads();
+            if (vec) {
+                int ne = 0;
+                for (int sb = 0; sb < nb * tpx; sb += NT) {
+                    const int slot = sb + tid;
+                    const int j = slot / tpx, i = slot - j * tpx;
+                    const int t = lw + (b0 + j) * nblk;
+                    if (j >= nb || t >= A.ntiles) continue;
+                    const int f = t / tpf, rr = t - f * tpf, ty = rr / A.tiles_x, tx = rr - ty * A.tiles_x;
+                    const int row = i / segs, sg = i - row * segs;
+                    const int y = ty * A.TH + row, x = tx * A.TW + sg * 16;
+                    if (x >= W || y >= H) continue;
+                    const long long q = (long long)f * A.HW + (long long)y * W + x;
+                    const uint4 lv = *reinterpret_cast<const uint4 *>(A.label + q);
+                    int4 *dst = reinterpret_cast<int4 *>(A.shell + q);
+                    if ((lv.x | lv.y | lv.z | lv.w) == 0u) {
+                        const int4 rdb = make_int4(S_READABLE, S_READABLE, S_READABLE, S_READABLE);
+                        dst[0] = rdb;
+                        dst[1] = rdb;
+                        dst[2] = rdb;
+                        dst[3] = rdb;
+                        continue;
+                    }
+                    const uint32_t wd[4] = {lv.x, lv.y, lv.z, lv.w};
+                    int nh = 0;
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        int32_t c4[4];
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const uint32_t b = (wd[q4] >> (8 * jj)) & 0xffu;
+                            nh += b == 1u ? 1 : 0;
+                            ne += b > 2u ? 1 : 0;
+                            c4[jj] = b == 0u ? S_READABLE : b == 1u ? S_HOLE : S_BYSTANDER;
+                        }
+                        dst[q4] = make_int4(c4[0], c4[1], c4[2], c4[3]);
+                    }
+                    if (nh) atomicAdd(&s_tcnt[j], nh);
+                }
+                if (ne) atomicAdd(&s_err_n, ne);
+            } else
             for (int sb = 0; sb < nb * tpx; sb += kWinPerThread * NT) {
             uint8_t lab[kWinPerThread];
             long long pix[kWinPerThread];
@@ -241,7 +288,15 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     GF_TACC(5);
 
     // ---- passes of S shells -------------------------------------------------
-    const int total_hole = sum_x(ctl, XF_HOLE);
+    // hole total and the first pass's list lengths, in one round trip
+    if (tid < kXcd) {
+        s_pf[tid] = ld_ctl(ctl, xw(tid, XF_HOLE));
+        if (A.tile_track) s_seg[tid] = ld_ctl(ctl, xw(tid, XF_ACT + 0));
+    }
+    __syncthreads();
+    int total_hole = 0;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) total_hole += s_pf[x];
     long long total_filled = 0;
     int max_front = 0;  // kept by thread 0 of logical workgroup 0
     const int nG = NT / G;
@@ -262,8 +317,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         int32_t *cur_act = (p & 1) ? A.act1 : A.act0;
         int32_t *nxt_act = ((p & 1) ? A.act0 : A.act1) + (long long)xcd * A.ntiles;
         int32_t *nxt_cnt = &ctl[xw(xcd, XF_ACT + (p + 1) % 3)];
-        if (A.tile_track && tid < kXcd) s_seg[tid] = ld_ctl(ctl, xw(tid, XF_ACT + p % 3));
-        __syncthreads();
+        __syncthreads();  // s_seg holds this pass's list lengths
         int n_tiles_pass = A.ntiles;
         if (A.tile_track) {
             n_tiles_pass = 0;
@@ -566,7 +620,15 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         grid_sync(ctl, grid);
         GF_TACC(5);
         GF_TCNT(10, 1);
-        const int fills = sum_x(ctl, XF_PFILL + p % 3);
+        // this pass's fills and the next pass's list lengths, in one round trip
+        if (tid < kXcd) {
+            s_pf[tid] = ld_ctl(ctl, xw(tid, XF_PFILL + p % 3));
+            if (A.tile_track) s_seg[tid] = ld_ctl(ctl, xw(tid, XF_ACT + (p + 1) % 3));
+        }
+        __syncthreads();
+        int fills = 0;
+#pragma unroll
+        for (int x = 0; x < kXcd; ++x) fills += s_pf[x];
         if (lw == 0 && tid == 0) {  // front sizes of the pass; the half is reused two passes on
             for (int j = 0; j < Sp && j < 32; ++j) {
                 int32_t *cw = &ctl[G_FRONT + (p & 1) * 32 + j];
