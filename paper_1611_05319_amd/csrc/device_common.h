@@ -228,6 +228,27 @@ __device__ inline void wave_count(bool pred, int *counter) {
     if (m != 0ull && lane_id() == __ffsll((long long)m) - 1) atomicAdd(counter, (int)__popcll(m));
 }
 
+// sum / maximum over the wavefront, added to an LDS counter by one lane
+__device__ inline void wave_add(int v, int *counter) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (v != 0 && lane_id() == 0) atomicAdd(counter, v);
+}
+__device__ inline void wave_max(int v, int *counter) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    if (v != 0 && lane_id() == 0) atomicMax(counter, v);
+}
+
+// q = i / d for 0 <= i < 2^20 and 0 < d < 2^20, from a binary32 reciprocal
+// r = 1 / d: the estimate is within one of the quotient and one step fixes it
+__device__ inline int div_small(int i, int d, float r) {
+    int q = (int)((float)i * r);
+    const int m = i - q * d;
+    q += (m >= d ? 1 : 0) - (m < 0 ? 1 : 0);
+    return q;
+}
+
 // readable at shell k: -1 (readable from the start) or filled in a shell < k
 __device__ inline bool readable(int32_t s, int k) { return (unsigned)(s + 1) <= (unsigned)k; }
 

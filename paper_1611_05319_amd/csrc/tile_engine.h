@@ -140,6 +140,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     const int tid = threadIdx.x;
     const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
     const int CP = padded_channels(C);  // channels per window pixel
+    const float rWW = 1.0f / (float)WW;  // window rows by div_small
     int32_t *st = reinterpret_cast<int32_t *>(smem);
     TS *col = reinterpret_cast<TS *>(smem + align16((size_t)WN * 4));
     float2 *gd = reinterpret_cast<float2 *>(smem + align16((size_t)WN * 4) +
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int i = base + tid + r * NT;
                     code[r] = S_BYSTANDER;
                     if (i < WN) {
-                        const int wy = i / WW, wx = i - wy * WW;
+                        const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
                         const int x = ox0 + wx, y = oy0 + wy;
                         if (x >= 0 && x < W && y >= 0 && y < H) {
                             const int32_t s = S[y * W + x];
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     if (i < WN) {
                         const bool known = code[r] == kKnown;
                         st[i] = known ? S_READABLE : code[r];
-                        const int wy = i / WW, wx = i - wy * WW;
+                        const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
                         const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
                         if (known || code[r] == S_READABLE) {
                             const TS *src = known ? Ui : U;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int i = base + tid;
                     bool act = false;
                     if (i < WN && st[i] == S_HOLE) {
-                        const int wy = i / WW, wx = i - wy * WW;
+                        const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
                         if (halo_dist(wx, wy) <= (Sp - 1) * rd) {
 #pragma unroll
                             for (int d = 0; d < 9; ++d) {
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             for (int j = 0; j < Sp; ++j) {
                 // fill one window pixel with a group; returns ready, sets the counters
                 auto fill_one = [&](int wi, bool &filled_here, bool &interior) -> bool {
-                    const int Y = wi / WW, X = wi - Y * WW;
+                    const int Y = div_small(wi, WW, rWW), X = wi - Y * WW;
                     const float2 gv = gd[wi];
                     double val[4];
                     const bool ok = fill_core<TS, G>(view, X, Y, (double)gv.x, (double)gv.y,
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         bool filled_here = false, interior = false;
                         if (item < n) {
                             const int wi = list[item];
-                            const int Y = wi / WW, X = wi - Y * WW;
+                            const int Y = div_small(wi, WW, rWW), X = wi - Y * WW;
                             if (halo_dist(X, Y) <= band) {  // else it cannot reach the interior
                                 GF_RT_BEGIN(rt_fill);
                                 const bool ok = fill_one(wi, filled_here, interior);
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         const int i = base + tid;
                         bool act = false;
                         if (i < WN && st[i] == S_HOLE) {
-                            const int wy = i / WW, wx = i - wy * WW;
+                            const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
                             if (halo_dist(wx, wy) <= (Sp - 1 - j) * rd) {
 #pragma unroll
                                 for (int d = 0; d < 9; ++d) {
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                 TS *O = reinterpret_cast<TS *>(A.out) + (long long)f * A.HW * C;
                 int32_t *Sw = A.shell + (long long)f * A.HW;
                 for (int i = tid; i < tw * th; i += NT) {
-                    const int ly = i / tw, lx = i - ly * tw;
+                    const int ly = div_small(i, tw, 1.0f / (float)tw), lx = i - ly * tw;
                     const int wi = (ly + A.Hh) * WW + (lx + A.Hh);
                     const int v = st[wi];
                     const int y = ty * A.TH + ly, x = tx * A.TW + lx;
@@ -566,9 +567,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                         ++nr;
                     }
                 }
-                if (nf) atomicAdd(&s_r[0], nf);
-                if (nr) atomicAdd(&s_r[1], nr);
-                if (km) atomicMax(&s_r[2], km);
+                wave_add(nf, &s_r[0]);
+                wave_add(nr, &s_r[1]);
+                wave_max(km, &s_r[2]);
                 __syncthreads();
                 const int tf = s_r[0];
                 if (tid == 0) {
