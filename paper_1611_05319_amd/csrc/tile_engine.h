@@ -136,6 +136,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
     __shared__ int s_seg[kXcd];     // this pass's active-tile list length per XCD
     __shared__ int s_pf[kXcd];      // the pass's fills per XCD
+    __shared__ int s_nbhole[9];     // hole counts of the tile's 3 x 3 neighbourhood
 
     const int tid = threadIdx.x;
     const int WN = A.WN, WW = A.WW, C = A.C, W = A.W, H = A.H;
@@ -339,6 +340,14 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
             const int32_t *S = A.shell + (long long)f * A.HW;
             const TS *U = reinterpret_cast<const TS *>(A.out) + (long long)f * A.HW * C;
             const TS *Ui = reinterpret_cast<const TS *>(A.in) + (long long)f * A.HW * C;
+            // hole counts of the 3 x 3 tile neighbourhood, needed by the bookkeeping
+            // at the end of the tile: loaded now, beside the window
+            int nbh = 0;
+            if (A.tile_track && tid < 9) {
+                const int nx = tx + tid % 3 - 1, ny = ty + tid / 3 - 1;
+                if (nx >= 0 && nx < A.tiles_x && ny >= 0 && ny < A.tiles_y)
+                    nbh = A.t_hole[f * tpf + ny * A.tiles_x + nx];
+            }
             const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
             // 1. stage the window in two round trips: states (readable before the
             //    pass / bystander / hole; pixels filled by neighbours during this pass
@@ -380,6 +389,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     }
                 }
             }
+            if (tid < 9) s_nbhole[tid] = nbh;
             if (tid == 0) {
                 s_fn[0] = s_fn[1] = 0;
                 s_filled_j = 0;
@@ -574,9 +584,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                 const int tf = s_r[0];
                 if (tid == 0) {
                     A.t_rem[t] = s_r[1];
-                    if (tf) {
-                        A.t_fill[t] += tf;
-                        A.t_kmax[t] = max(A.t_kmax[t], s_r[2]);
+                    if (tf) {  // no value returned: nothing waits for these
+                        atomicAdd(&A.t_fill[t], tf);
+                        atomicMax(&A.t_kmax[t], s_r[2]);
                         s_pass_fill += tf;
                         s_pass_kmax = max(s_pass_kmax, s_r[2]);
                     }
@@ -590,7 +600,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int nx = tx + tid % 3 - 1, ny = ty + tid / 3 - 1;
                     if (nx >= 0 && nx < A.tiles_x && ny >= 0 && ny < A.tiles_y) {
                         const int n = f * tpf + ny * A.tiles_x + nx;
-                        if (A.t_hole[n] > 0 && atomicMax(&A.t_mark[n], p + 1) < p + 1)
+                        if (s_nbhole[tid] > 0 && atomicMax(&A.t_mark[n], p + 1) < p + 1)
                             stage_push(stage, n, nxt_act, nxt_cnt);
                     }
                 }
