@@ -11,6 +11,7 @@ single-frame launches, forward vs forward + backward on 16 x 512 x 512.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --profile          (fill steps only, for rocprofv3 runs)
+    python bench.py --profile-batched  (64-frame batch fill steps only)
 """
 
 from __future__ import annotations
@@ -140,12 +141,37 @@ def time_steps(fn, steps, warmup, torch):
     return wall_ms, a.elapsed_time(b) / steps
 
 
+def profile_batched(args):
+    """The 64-frame binary16 batch alone, one launch per step, with the launch
+    shape the autotuner picks (as in the full run's batched leg)."""
+    w4 = syn.config4()
+    import torch
+
+    import paper_1611_05319_amd as gf
+    from paper_1611_05319_amd import autotune
+
+    dev = torch.device("cuda:0")
+    i4 = torch.from_numpy(w4.image).to(dev)
+    l4 = torch.from_numpy(w4.label).to(dev)
+    g4 = torch.from_numpy(w4.guide).to(dev)
+    p4 = autotune.tune(i4, l4, g4, gf.Params(eps=w4.eps, mu=w4.mu), reps=3)
+    plan = gf.FillPlan(i4, l4, g4, p4)
+    plan.run()
+    torch.cuda.synchronize()
+    st = gf.stats_fields(plan.stats)
+    wall, ev = time_steps(plan.run, args.steps, args.warmup, torch)
+    print(json.dumps({"profile": "batched", "steps": args.steps, "fill_event_ms": ev, "wall_ms": wall,
+                      "launch": launch_fields(p4), "K": st["K"], "filled": st["filled"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--profile", action="store_true", help="fill steps only (for rocprofv3)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="64-frame batch fill steps only (for rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=512, help="plain copy size in --profile mode")
@@ -154,6 +180,10 @@ def main():
         print("bench.py: this build runs on one GPU only (frames shard with no exchange; "
               "see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_batched:
+        profile_batched(args)
+        return
 
     # ---- inputs (generated before the device is touched) ---------------------
     w2 = syn.config2()
