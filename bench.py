@@ -12,6 +12,7 @@ single-frame launches, forward vs forward + backward on 16 x 512 x 512.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --profile          (fill steps only, for rocprofv3 runs)
     python bench.py --profile-batched  (64-frame batch fill steps only)
+    python bench.py --profile-grad     (16 x 512^2 forward + backward steps only)
 """
 
 from __future__ import annotations
@@ -164,6 +165,36 @@ def profile_batched(args):
                       "launch": launch_fields(p4), "K": st["K"], "filled": st["filled"]}), flush=True)
 
 
+def profile_grad(args):
+    """Forward (recording the fill order) then backward on the 16-frame
+    512 x 512 workload, one launch each per step, as in the full run."""
+    w5, _ = syn.config5()
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    dev = torch.device("cuda:0")
+    i5 = torch.from_numpy(w5.image).to(dev)
+    l5 = torch.from_numpy(w5.label).to(dev)
+    g5 = torch.from_numpy(w5.guide).to(dev)
+    plan_f = gf.FillPlan(i5, l5, g5, gf.Params(eps=w5.eps, mu=w5.mu), record_order=True)
+    plan_f.run()
+    torch.cuda.synchronize()
+    K5 = int(plan_f.stats[0].item())
+    gi = torch.empty_like(i5)
+    gg = torch.empty(i5.shape[:3] + (2,), dtype=torch.float32, device=dev)
+    bw = gf.BackwardPlan(plan_f, torch.randn_like(i5), gi, gg, K5)
+
+    def fwd_bwd():
+        plan_f.run()
+        bw.run()
+
+    wall_f, ev_f = time_steps(plan_f.run, args.steps, args.warmup, torch)
+    wall_fb, ev_fb = time_steps(fwd_bwd, args.steps, args.warmup, torch)
+    print(json.dumps({"profile": "grad", "steps": args.steps, "fwd_ms": wall_f, "fwd_bwd_ms": wall_fb,
+                      "fwd_event_ms": ev_f, "fwd_bwd_event_ms": ev_fb, "K": K5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +203,8 @@ def main():
     ap.add_argument("--profile", action="store_true", help="fill steps only (for rocprofv3)")
     ap.add_argument("--profile-batched", action="store_true",
                     help="64-frame batch fill steps only (for rocprofv3)")
+    ap.add_argument("--profile-grad", action="store_true",
+                    help="16 x 512^2 forward + backward steps only (for rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=512, help="plain copy size in --profile mode")
@@ -183,6 +216,9 @@ def main():
 
     if args.profile_batched:
         profile_batched(args)
+        return
+    if args.profile_grad:
+        profile_grad(args)
         return
 
     # ---- inputs (generated before the device is touched) ---------------------
