@@ -53,7 +53,8 @@ def _load():
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         lib.gfo_fill.argtypes = [ctypes.c_int] * 4 + [P, P, P, ctypes.c_double, ctypes.c_double,
-                                                      ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                      ctypes.c_double, ctypes.c_double,
+                                                      ctypes.c_int, ctypes.c_int,
                                                       ctypes.c_int, P, P, P, P, P, ctypes.c_int,
                                                       ctypes.c_int]
         lib.gfo_fill.restype = ctypes.c_int
@@ -120,10 +121,11 @@ class Result:
 
 def fill(img, label, guide, eps: float = 3.0, mu: float = 50.0, c: float = -1.0,
          ghost: bool = True, max_shells: int = 0, storage: str = "f64",
-         threads: int | None = None, hist_cap: int = 4096) -> Result:
+         threads: int | None = None, hist_cap: int = 4096, c2: float = -1.0) -> Result:
     """Run the FP64 oracle.  img: (B x) H x W x C; label: (B x) H x W uint8
     (0 readable, 1 inpaint, 2 bystander); guide: (B x) H x W x 2 (gx, gy).
-    `c < 0` selects onion order; `storage` rounds stored values ('f32', 'f16')."""
+    `c < 0` selects onion order; `c2 >= 0` adds eqn:ready2's data term
+    |g| > c2; `storage` rounds stored values ('f32', 'f16')."""
     lib = _load()
     img, label, guide, squeeze = _as_batch(img, label, guide)
     B, H, W, C = img.shape
@@ -140,7 +142,7 @@ def fill(img, label, guide, eps: float = 3.0, mu: float = 50.0, c: float = -1.0,
     if threads is None:
         threads = int(os.environ.get("GFO_THREADS", os.cpu_count() or 1))
     rc = lib.gfo_fill(B, H, W, C, _ptr(u_in), _ptr(lab), _ptr(g), float(eps), float(mu), float(c),
-                      int(bool(ghost)), int(max_shells), STORAGE[storage], _ptr(u), _ptr(s),
+                      float(c2), int(bool(ghost)), int(max_shells), STORAGE[storage], _ptr(u), _ptr(s),
                       _ptr(stats), _ptr(fh), _ptr(ph), hist_cap, int(threads))
     if rc != 0:
         raise ValueError(f"oracle fill failed with code {rc}")

@@ -37,7 +37,13 @@
  *  - Ready (Sec. 3.4): onion order (c < 0) fills every active pixel that has
  *    at least one readable point; smart order uses the confidence
  *    C = sum_readable w / sum_all w (eqn:confidence, denominator over the
- *    whole rotated ball) and ready = 1(C > c) (eqn:ready).
+ *    whole rotated ball) and ready = 1(C > c) (eqn:ready).  The data-term
+ *    variant (eqn:ready2) multiplies ready by 1(|g(x)| > c2) while the guided
+ *    region can still advance; the paper reverts to eqn:ready once the region
+ *    |g| > 0 has been filled.  Reading: the revert happens at the first shell
+ *    in which the data term leaves nothing ready (which is the shell after the
+ *    region's last pixel, or an earlier one if the rest of the region cannot
+ *    be reached), and that shell is then evaluated with eqn:ready.
  *
  * Readings where the paper is silent (the same list is kept with the design
  * notes): (0,0) is not in the ball; R acts with the unit vector g/|g|; the
@@ -265,6 +271,10 @@ static int eval_pixel(const prob_t *P, const double *u, const int32_t *s, int i,
  *                       pixel is never filled)
  *   label     B*H*W     0 readable, 1 inpaint (D_h), 2 bystander (B_h)
  *   guide     B*H*W*2   (gx, gy), read on the hole only
+ *   c         < 0: onion order; >= 0: smart order threshold (eqn:ready)
+ *   c2        < 0: no data term; >= 0: eqn:ready2's data term |g(x)| > c2
+ *             gates ready until a shell fills nothing; from that shell on
+ *             (taken again) eqn:ready alone decides
  *   storage   0: keep FP64; 1: round every stored value to binary32;
  *             2: round to binary16 (inputs and each filled value)
  *   img_out   B*H*W*C, shell_out B*H*W (-1 readable, -2 bystander, k >= 0
@@ -276,8 +286,8 @@ static int eval_pixel(const prob_t *P, const double *u, const int32_t *s, int i,
  * Returns GFO_OK, or GFO_EINVAL / GFO_ELABEL / GFO_ENOMEM.
  */
 int gfo_fill(int B, int H, int W, int C, const double *img_in, const uint8_t *label,
-             const double *guide, double eps, double mu, double c, int ghost, int max_shells,
-             int storage, double *img_out, int32_t *shell_out, int64_t *stats,
+             const double *guide, double eps, double mu, double c, double c2, int ghost,
+             int max_shells, int storage, double *img_out, int32_t *shell_out, int64_t *stats,
              int64_t *front_hist, int64_t *fill_hist, int hist_cap, int nthreads)
 {
     if (B < 0 || H <= 0 || W <= 0 || C <= 0 || !(eps > 0) || !(mu > 0)) return GFO_EINVAL;
@@ -315,6 +325,7 @@ int gfo_fill(int B, int H, int W, int C, const double *img_in, const uint8_t *la
         if (rc != GFO_OK) break;
         int64_t n_hole = nD, filled_total = 0, max_front = 0, ties = 0;
         int K = 0;
+        int data_phase = c2 >= 0.0; /* eqn:ready2 gates ready until a shell fills nothing */
         for (int k = 0;; ++k) {
             if (nD == 0) break;                           /* D^(k) empty */
             if (max_shells > 0 && k >= max_shells) break; /* caller's stop */
@@ -332,6 +343,10 @@ int gfo_fill(int B, int H, int W, int C, const double *img_in, const uint8_t *la
                     ready[e] = 0;
                     if (!active[e]) continue;
                     ++n_active;
+                    if (data_phase) { /* data term D(x) = |g(x)| of eqn:ready2 */
+                        double gx = P.g[2 * (size_t)q], gy = P.g[2 * (size_t)q + 1];
+                        if (!(sqrt(gx * gx + gy * gy) > c2)) continue;
+                    }
                     double conf;
                     ready[e] = (unsigned char)eval_pixel(&P, u, s, i, j, k, vals + (size_t)e * C,
                                                          &conf, Gbuf, rd);
@@ -355,6 +370,14 @@ int gfo_fill(int B, int H, int W, int C, const double *img_in, const uint8_t *la
             if (front_hist && k < hist_cap) front_hist[(size_t)b * hist_cap + k] = n_active;
             if (fill_hist && k < hist_cap) fill_hist[(size_t)b * hist_cap + k] = nF;
             if (n_active > max_front) max_front = n_active;
+            if (nF == 0 && data_phase) {
+                /* the data term holds every front pixel back: from this shell on
+                   eqn:ready alone decides, and shell k is taken again (nothing
+                   was committed, D^(k) is unchanged) */
+                data_phase = 0;
+                --k;
+                continue;
+            }
             ties += n_ties;
             if (nF == 0) break; /* nothing ready: the state can no longer change */
             K = k + 1;

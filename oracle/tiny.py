@@ -16,7 +16,10 @@ own terms, with Python sets:
 * the rotated ball R(B_eps(x)) with R taking (0,1) to g/|g| (Sec. 3.1), the
   lattice ball when g = 0 or in coherence-transport mode;
 * weights eqn:weight, confidence eqn:confidence, ready eqn:ready (onion order
-  when c < 0: every active pixel with a usable point is filled);
+  when c < 0: every active pixel with a usable point is filled); with c2 >= 0
+  the data term of eqn:ready2, D(x) = |g(x)| > c2, gates ready until a shell
+  fills nothing, after which eqn:ready alone decides (that shell is taken
+  again);
 * the shell update of Algorithm 1 with the state of shell k frozen while
   shell k is computed.
 
@@ -52,7 +55,7 @@ def rotated_offset(gx: float, gy: float, n: int, m: int, ghost: bool):
     return (float(n), float(m))
 
 
-def fill(img, label, guide, eps=3.0, mu=50.0, c=-1.0, ghost=True, max_shells=0):
+def fill(img, label, guide, eps=3.0, mu=50.0, c=-1.0, ghost=True, max_shells=0, c2=-1.0):
     """img: H x W x C nested lists or array; label: H x W; guide: H x W x 2.
     Returns (u as H x W x C list of floats, shell map as H x W list, K)."""
     H = len(label)
@@ -70,6 +73,7 @@ def fill(img, label, guide, eps=3.0, mu=50.0, c=-1.0, ghost=True, max_shells=0):
     nbr8 = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dx, dy) != (0, 0)]
     K = 0
     k = 0
+    data_phase = c2 >= 0.0
     while True:
         if not Dk:
             break
@@ -81,6 +85,8 @@ def fill(img, label, guide, eps=3.0, mu=50.0, c=-1.0, ghost=True, max_shells=0):
         new_vals = {}
         for (x, y) in active:
             gx, gy = float(guide[y][x][0]), float(guide[y][x][1])
+            if data_phase and not (math.sqrt(gx * gx + gy * gy) > c2):
+                continue
             pts = []
             for (n, m) in offs:
                 ox, oy = rotated_offset(gx, gy, n, m, ghost)
@@ -128,6 +134,9 @@ def fill(img, label, guide, eps=3.0, mu=50.0, c=-1.0, ghost=True, max_shells=0):
                     acc[ch] += w * val[ch]
             new_vals[(x, y)] = [acc[ch] / S for ch in range(C)]
         if not new_vals:
+            if data_phase:  # the data term holds everything back: eqn:ready from here on
+                data_phase = False
+                continue
             break
         for p, v in new_vals.items():
             u[p] = v

@@ -388,3 +388,79 @@ def test_smart_order_threshold_on_a_straight_edge(guide, readable, eps, mu):
     inner = slice(int(math.ceil(eps)), W - int(math.ceil(eps)))
     assert (below.shell[4, inner] == 0).all()
     assert (above.shell[4, inner] != 0).all()
+
+
+# ----------------------------------------------------------------------------
+# the data term (Sec. 3.4, eqn:ready2): ready = 1(|g| > c2) 1(C > c1) while
+# the guided region can still advance, eqn:ready afterwards
+
+
+def _guided_band_problem(seed=3, H=48, W=56):
+    """A hole whose left columns carry a guide (|g| = 1) and whose right
+    columns carry none, both touching readable pixels."""
+    rng = np.random.default_rng(seed)
+    img = rng.uniform(0, 1, size=(H, W, 3)).astype(np.float32)
+    lab = np.zeros((H, W), np.uint8)
+    lab[8:40, 10:46] = 1
+    th = rng.uniform(0, math.pi, size=(H, W))
+    g = np.stack([np.cos(th), np.sin(th)], -1).astype(np.float32)
+    g[:, 28:] = 0.0
+    g = np.where((lab == 1)[..., None], g, np.float32(0))
+    return img, lab, g
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.05])
+def test_data_term_fills_the_guided_region_first(c):
+    img, lab, g = _guided_band_problem()
+    r = oracle.fill(img, lab, g, c=c, c2=0.0)
+    guided = (lab == 1) & (np.hypot(g[..., 0], g[..., 1]) > 0)
+    plain = (lab == 1) & ~guided
+    assert (r.shell[lab == 1] >= 0).all()
+    # every guided pixel is filled in a shell before any unguided pixel
+    assert r.shell[guided].max() < r.shell[plain].min()
+    base = oracle.fill(img, lab, g, c=c)
+    assert r.K > base.K  # the unguided region waited
+    # colours stay inside the convex hull of the known values
+    known = img[lab == 0]
+    assert (r.u[lab == 1] >= known.min(0) - 1e-12).all() and (r.u[lab == 1] <= known.max(0) + 1e-12).all()
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.05])
+def test_data_term_is_inert_when_the_guide_is_everywhere_or_nowhere(c):
+    img, lab, g = _random_problem(11)
+    g_all = g.copy()
+    zero = (lab == 1) & (np.hypot(g[..., 0], g[..., 1]) == 0)
+    g_all[zero] = np.array([0.6, 0.8], np.float32)
+    for gg in (g_all, np.zeros_like(g)):
+        a = oracle.fill(img, lab, gg, c=c)
+        b = oracle.fill(img, lab, gg, c=c, c2=0.0)
+        np.testing.assert_array_equal(b.shell, a.shell)
+        np.testing.assert_array_equal(b.u, a.u)
+
+
+def test_data_term_switches_when_the_guided_region_is_unreachable():
+    # one guided pixel deep inside an unguided hole: nothing is ready at shell
+    # 0 under the data term, so eqn:ready decides from shell 0 on
+    img, lab, g = _guided_band_problem()
+    g2 = np.zeros_like(g)
+    g2[24, 28] = (1.0, 0.0)
+    a = oracle.fill(img, lab, g2)
+    b = oracle.fill(img, lab, g2, c2=0.0)
+    np.testing.assert_array_equal(b.shell, a.shell)
+
+
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_data_term_matches_set_transcription(seed):
+    from oracle import tiny
+
+    rng = np.random.default_rng(2000 + seed)
+    H, W = (int(v) for v in rng.integers(7, 18, size=2))
+    img, lab, g = syn.random_tiny(rng, H, W, C=2, p_hole=float(rng.uniform(0.3, 0.6)),
+                                  p_bystander=float(rng.uniform(0.0, 0.15)), zero_guide_frac=0.4)
+    c = -1.0 if seed % 2 else 0.05
+    c2 = 0.0 if seed % 3 else 0.5
+    r = oracle.fill(img, lab, g, eps=3.0, mu=20.0, c=c, c2=c2)
+    tu, ts, tK = tiny.fill(img, lab, g, eps=3.0, mu=20.0, c=c, c2=c2)
+    np.testing.assert_array_equal(np.array(ts, dtype=np.int32), r.shell)
+    assert tK == r.K
+    np.testing.assert_allclose(np.array(tu), r.u, rtol=0, atol=1e-12)
