@@ -7,12 +7,14 @@ the device before the timed region.  The JSON line reports Mpix filled per
 second, the fill call's algorithmic HBM bytes against the 8 TB/s peak, the
 FP64 CPU oracle on the host cores, and the side comparisons named by the
 metric: tracked vs untracked, one batched launch of 64 fp16 frames vs 64
-single-frame launches, forward vs forward + backward on 16 x 512 x 512.
+single-frame launches, forward vs forward + backward on 16 x 512 x 512, and
+the 3840x2160 deep front (eps = 5, about 100 shells).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --profile          (fill steps only, for rocprofv3 runs)
     python bench.py --profile-batched  (64-frame batch fill steps only)
     python bench.py --profile-grad     (16 x 512^2 forward + backward steps only)
+    python bench.py --profile-deep     (3840x2160 deep-front fill steps only)
 """
 
 from __future__ import annotations
@@ -32,6 +34,9 @@ import numpy as np  # noqa: E402
 import synthetic as syn  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# what the fill computes in: binary32 storage; FP64 ghost geometry, weights
+# and weighted sums; FP32 bilinear interpolation of each ghost value
+DTYPE = "f64+f32 (binary32 storage; FP64 geometry, weights and sums; FP32 bilinear values)"
 METRIC = "Mpix filled/s + HBM GB/s fraction @1080p eps=3; batched vs plain; fwd+bwd ms"
 
 
@@ -142,6 +147,44 @@ def time_steps(fn, steps, warmup, torch):
     return wall_ms, a.elapsed_time(b) / steps
 
 
+def deep_front(w3, torch, gf, autotune, dev, args):
+    """The 4K deep-front fill (about 100 shells): Mpix filled/s, us per shell
+    and the algorithmic-byte roofline of the autotuned launch."""
+    B, H, W, C = w3.image.shape
+    i3 = torch.from_numpy(w3.image).to(dev)
+    l3 = torch.from_numpy(w3.label).to(dev)
+    g3 = torch.from_numpy(w3.guide).to(dev)
+    p3 = autotune.tune(i3, l3, g3, gf.Params(eps=w3.eps, mu=w3.mu), reps=3)
+    plan = gf.FillPlan(i3, l3, g3, p3)
+    plan.run()
+    torch.cuda.synchronize()
+    st = gf.stats_fields(plan.stats)
+    steps = max(5, args.steps // 4)
+    wall, ev = time_steps(plan.run, steps, 2, torch)
+    nbytes = algorithmic_bytes(B, H, W, C, 4, st["hole"])
+    achieved = nbytes / (ev * 1e-3) / 1e9
+    return {"workload": "3840x2160 RGB binary32, 200-px wiggly band + 20 discs, eps=5, mu=100",
+            "hole_px": st["hole"], "filled_px": st["filled"], "shells": st["K"],
+            "launch": launch_fields(p3), "ms_per_step": round(wall, 4),
+            "mpix_filled_per_s": round(st["filled"] / (wall * 1e-3) / 1e6, 2),
+            "us_per_shell": round(ev * 1e3 / max(st["K"], 1), 3),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                         "algorithmic_bytes": nbytes, "event_ms_per_launch": round(ev, 5)}}
+
+
+def profile_deep(args):
+    """The 4K deep-front fill alone, one launch per step, autotuned launch."""
+    w3 = syn.config3()
+    import torch
+
+    import paper_1611_05319_amd as gf
+    from paper_1611_05319_amd import autotune
+
+    dev = torch.device("cuda:0")
+    print(json.dumps({"profile": "deep", **deep_front(w3, torch, gf, autotune, dev, args)}), flush=True)
+
+
 def profile_batched(args):
     """The 64-frame binary16 batch alone, one launch per step, with the launch
     shape the autotuner picks (as in the full run's batched leg)."""
@@ -177,13 +220,16 @@ def profile_grad(args):
     i5 = torch.from_numpy(w5.image).to(dev)
     l5 = torch.from_numpy(w5.label).to(dev)
     g5 = torch.from_numpy(w5.guide).to(dev)
-    plan_f = gf.FillPlan(i5, l5, g5, gf.Params(eps=w5.eps, mu=w5.mu), record_order=True)
+    from paper_1611_05319_amd import autotune
+
+    p5 = autotune.tune(i5, l5, g5, gf.Params(eps=w5.eps, mu=w5.mu), reps=3)
+    plan_f = gf.FillPlan(i5, l5, g5, p5)
     plan_f.run()
     torch.cuda.synchronize()
     K5 = int(plan_f.stats[0].item())
     gi = torch.empty_like(i5)
     gg = torch.empty(i5.shape[:3] + (2,), dtype=torch.float32, device=dev)
-    bw = gf.BackwardPlan(plan_f, torch.randn_like(i5), gi, gg, K5)
+    bw = gf.BackwardPlan(plan_f, torch.randn_like(i5), gi, gg)
 
     def fwd_bwd():
         plan_f.run()
@@ -192,7 +238,8 @@ def profile_grad(args):
     wall_f, ev_f = time_steps(plan_f.run, args.steps, args.warmup, torch)
     wall_fb, ev_fb = time_steps(fwd_bwd, args.steps, args.warmup, torch)
     print(json.dumps({"profile": "grad", "steps": args.steps, "fwd_ms": wall_f, "fwd_bwd_ms": wall_fb,
-                      "fwd_event_ms": ev_f, "fwd_bwd_event_ms": ev_fb, "K": K5}), flush=True)
+                      "fwd_event_ms": ev_f, "fwd_bwd_event_ms": ev_fb, "K": K5,
+                      "launch": launch_fields(p5)}), flush=True)
 
 
 def main():
@@ -205,6 +252,8 @@ def main():
                     help="64-frame batch fill steps only (for rocprofv3)")
     ap.add_argument("--profile-grad", action="store_true",
                     help="16 x 512^2 forward + backward steps only (for rocprofv3)")
+    ap.add_argument("--profile-deep", action="store_true",
+                    help="3840x2160 deep-front fill steps only (for rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-mb", type=int, default=512, help="plain copy size in --profile mode")
@@ -220,11 +269,15 @@ def main():
     if args.profile_grad:
         profile_grad(args)
         return
+    if args.profile_deep:
+        profile_deep(args)
+        return
 
     # ---- inputs (generated before the device is touched) ---------------------
     w2 = syn.config2()
     extras = not (args.no_extras or args.profile)
     if extras:
+        w3 = syn.config3()
         w4 = syn.config4()
         w5, theta5 = syn.config5()
     base = None
@@ -278,7 +331,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE,
         "data": "synthetic",
         "config": {"workload": "plain fill 1920x1080 RGB, binary32 storage, 6 silhouette bands "
                                "5-20 px, spline/structure-tensor guide, eps=3, mu=50, onion "
@@ -332,19 +385,21 @@ def main():
                           "hbm_gbs": round(nb4 / (ev_b * 1e-3) / 1e9, 1),
                           "hbm_frac": round(nb4 / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del i4, l4, g4, plan_b, plans_1
+        # deep front: 3840x2160, one 200-px band plus 20 discs, eps = 5, mu = 100
+        out["deep_front"] = deep_front(w3, torch, gf, autotune, dev, args)
         # forward vs forward + backward (reverse-shell adjoint)
         i5 = torch.from_numpy(w5.image).to(dev)
         l5 = torch.from_numpy(w5.label).to(dev)
         g5 = torch.from_numpy(w5.guide).to(dev)
-        p5 = gf.Params(eps=w5.eps, mu=w5.mu)
-        plan_f = gf.FillPlan(i5, l5, g5, p5, record_order=True)
+        p5 = autotune.tune(i5, l5, g5, gf.Params(eps=w5.eps, mu=w5.mu), reps=3)
+        plan_f = gf.FillPlan(i5, l5, g5, p5)
         plan_f.run()
         torch.cuda.synchronize()
         K5 = int(plan_f.stats[0].item())
         grad = torch.randn_like(i5)
         gi = torch.empty_like(i5)
         gg = torch.empty(i5.shape[:3] + (2,), dtype=torch.float32, device=dev)
-        bw = gf.BackwardPlan(plan_f, grad, gi, gg, K5)
+        bw = gf.BackwardPlan(plan_f, grad, gi, gg)
 
         def fwd_bwd():
             plan_f.run()
@@ -355,6 +410,7 @@ def main():
         wall_fb, _ = time_steps(fwd_bwd, steps5, 2, torch)
         out["fwd_bwd"] = {"workload": "16 x 512x512 RGB fp32, band masks 6-16 px, smooth angle "
                                       "field, eps=3, mu=50",
+                          "launch": launch_fields(p5),
                           "fwd_ms": round(wall_f, 4), "fwd_bwd_ms": round(wall_fb, 4),
                           "ratio": round(wall_fb / wall_f, 3), "shells": K5}
     print(json.dumps(out), flush=True)

@@ -20,8 +20,11 @@
  *     synchronously, device-side findings (label errors, unfilled pixels) in
  *     the stats array after the stream is synchronised.
  *   - Images are B x H x W x C, interleaved channels (HWC per frame), frames
- *     contiguous; element type GF_F32 (binary32) or GF_F16 (binary16 storage;
- *     arithmetic is FP64 in either case).  1 <= C <= 4.
+ *     contiguous; element type GF_F32 (binary32) or GF_F16 (binary16).  In
+ *     either case the ghost geometry, readable tests, weights and weighted
+ *     sums are FP64 and each ghost point's bilinear value is interpolated in
+ *     FP32 from the stored colours; results are rounded once to the storage
+ *     type.  1 <= C <= 4.
  *   - label: B x H x W uint8, 0 = readable, 1 = inpaint (D_h), 2 = bystander
  *     (B_h, neither filled nor read, Sec. 2.1).  Other values are reported
  *     as label errors and treated as bystanders.
@@ -118,7 +121,7 @@ size_t gf_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_param
  *   label, guide, shell_out: as above; shell_out is required.
  *   stats       int32[8 + 4*B], required.
  *   order_out   nullable; int32[B*H*W]: frame*H*W + pixel of every filled
- *               pixel, grouped by shell (the input of gf_fill_backward);
+ *               pixel, grouped by shell;
  *               needs engine GF_ENGINE_FRONT (else GF_EUNSUPPORTED).
  *   shell_offsets nullable (required with order_out); int32[kcap]: entry k is
  *               the start of shell k in order_out, entry K its end.  If
@@ -145,26 +148,33 @@ gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dty
 
 /*
  * Reverse-mode derivative of a completed fill (this build's extension; the
- * fill is linear in the known colours, Algorithm 1).  Replays the shells from
- * last to first over the forward's order_out / shell_offsets, recomputing the
- * ghost geometry and weights from the shell map instead of storing them.
+ * fill is linear in the known colours, Algorithm 1).  One persistent launch:
+ * the filled pixels are grouped by shell from the shell map (a counting sort
+ * inside the launch), then the shells are replayed from the last to the
+ * first, the ghost geometry, readable sets and weights recomputed from the
+ * shell map instead of stored.  Any engine's forward can precede it.
  *   grad_out    B*H*W*C binary32: dL/d img_out.
- *   img_out     the forward's output (dt), shell: its shell map.
- *   order, shell_offsets, K: the forward's order_out, shell_offsets and
- *               stats[GF_STAT_SHELLS].
+ *   img_out     the forward's output (dt); shell: its shell map.
+ *   label       not read (the shell map carries the labels' roles); may be NULL.
+ *   guide       the forward's guide.
+ *   K           shells to replay: the forward's stats[GF_STAT_SHELLS], or -1
+ *               to take max(shell) + 1 from the map on the device (no host
+ *               synchronisation).  Pixels with shell >= K are treated as never
+ *               filled.  -1 <= K <= H * W.
  *   grad_img    B*H*W*C binary32: dL/d img_in (readable and bystander pixels
- *               and never-filled hole pixels pass grad_out through; filled
- *               hole pixels get 0).  May equal grad_out.
+ *               and never-filled hole pixels pass grad_out through plus what
+ *               the fill propagates to them; filled hole pixels get 0).  May
+ *               equal grad_out.
  *   grad_guide  B*H*W*2 binary32: dL/d guide on filled pixels, 0 elsewhere.
  *   p           the forward's parameters (eps, mu, ghost are used).
+ *   workspace   >= gf_backward_workspace_size(...) bytes, 256-byte aligned,
+ *               zeroed before its first use (as for the forward).
  * Returns GF_OK or GF_EINVAL / GF_EUNSUPPORTED / GF_EDEVICE.
  */
 gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, int H, int W, int C,
                            gf_dtype dt, const uint8_t *label, const float *guide,
-                           const int32_t *shell, const int32_t *order,
-                           const int32_t *shell_offsets, int K, const gf_params *p,
-                           float *grad_img, float *grad_guide, void *workspace,
-                           size_t ws_bytes, void *stream);
+                           const int32_t *shell, int K, const gf_params *p, float *grad_img,
+                           float *grad_guide, void *workspace, size_t ws_bytes, void *stream);
 
 /* Bytes of workspace gf_fill_backward needs. */
 size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
@@ -182,7 +192,7 @@ const char *gf_status_string(gf_status s);
 /* Last HIP error text recorded by this thread (static thread-local storage). */
 const char *gf_last_error(void);
 
-/* ABI version: 1. */
+/* ABI version: 2. */
 int gf_version(void);
 
 #ifdef __cplusplus

@@ -23,7 +23,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_backward", "GuidefillFn",
+    "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_backward",
+    "GuidefillFn",
     "library_path", "load", "stats_fields", "tile_geometry", "ENGINE_TILED", "ENGINE_FRONT",
 ]
 
@@ -102,7 +103,7 @@ def load():
         lib.gf_fill_batched.restype = I
         lib.gf_fill.argtypes = [P, P, I, I, I, I, P, P, PP, P, P, P, Z, P]
         lib.gf_fill.restype = I
-        lib.gf_fill_backward.argtypes = [P, P, I, I, I, I, I, P, P, P, P, P, I, PP, P, P, P, Z, P]
+        lib.gf_fill_backward.argtypes = [P, P, I, I, I, I, I, P, P, P, I, PP, P, P, P, Z, P]
         lib.gf_fill_backward.restype = I
         lib.gf_status_string.argtypes = [I]
         lib.gf_status_string.restype = ctypes.c_char_p
@@ -278,14 +279,13 @@ def fill(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
 
 def fill_backward(grad_out: torch.Tensor, fwd: FillResult, label: torch.Tensor,
                   guide: torch.Tensor, params: Params | None = None,
-                  K: int | None = None, **kw):
-    """dL/d img_in and dL/d guide of a fill recorded with record_order=True.
-    Shapes B x H x W x C / B x H x W x 2.  Returns (grad_img, grad_guide)."""
+                  K: int | None = None, workspace: torch.Tensor | None = None, **kw):
+    """dL/d img_in and dL/d guide of a completed fill (any engine).  Shapes
+    B x H x W x C / B x H x W x 2.  K: shells to replay (default: taken from
+    the shell map on the device).  Returns (grad_img, grad_guide)."""
     p = params or Params()
     if kw:
         p = Params(**{**p.__dict__, **kw})
-    if fwd.order is None:
-        raise ValueError("the forward must be run with record_order=True")
     img_out = fwd.out
     if img_out.dim() == 3:
         img_out = img_out.unsqueeze(0)
@@ -297,20 +297,15 @@ def fill_backward(grad_out: torch.Tensor, fwd: FillResult, label: torch.Tensor,
         raise TypeError("grad_out must be float32")
     B, H, W, C = img_out.shape
     lib = load()
-    if K is None:
-        K = int(fwd.stats[STAT_SHELLS].item())
-    if bool(fwd.stats[STAT_ORDER_TRUNC].item()):
-        raise RuntimeError("the forward's shell offsets were truncated (raise kcap)")
     grad_img = torch.empty_like(grad_out)
     grad_guide = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
     cp = p.c_struct()
     dt = _dtype_code(img_out)
     nbytes = lib.gf_backward_workspace_size(B, H, W, C, dt, ctypes.byref(cp))
-    ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    ws = workspace if workspace is not None else torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
     rc = lib.gf_fill_backward(_ptr(grad_out), _ptr(img_out), B, H, W, C, dt, _ptr(label),
-                              _ptr(guide), _ptr(shell), _ptr(fwd.order), _ptr(fwd.shell_offsets),
-                              int(K), ctypes.byref(cp), _ptr(grad_img), _ptr(grad_guide), _ptr(ws),
-                              ws.numel(), _stream_ptr(dev))
+                              _ptr(guide), _ptr(shell), -1 if K is None else int(K), ctypes.byref(cp),
+                              _ptr(grad_img), _ptr(grad_guide), _ptr(ws), ws.numel(), _stream_ptr(dev))
     _check(rc, "gf_fill_backward")
     return grad_img, grad_guide
 
@@ -362,13 +357,12 @@ class FillPlan:
 
 
 class BackwardPlan:
-    """Preallocated reverse-shell call for a FillPlan made with record_order=True:
-    grad_out -> (grad_img, grad_guide) with the forward's shell count K."""
+    """Preallocated reverse-shell call for a FillPlan (any engine):
+    grad_out -> (grad_img, grad_guide).  K: shells to replay (default: taken
+    from the shell map on the device)."""
 
     def __init__(self, fwd: FillPlan, grad_out: torch.Tensor, grad_img: torch.Tensor,
-                 grad_guide: torch.Tensor, K: int):
-        if fwd.order is None:
-            raise ValueError("the forward plan must record the fill order")
+                 grad_guide: torch.Tensor, K: int = -1):
         _require_device(grad_out, grad_img, grad_guide)
         B, H, W, C = fwd.shape
         lib = load()
@@ -377,9 +371,8 @@ class BackwardPlan:
         self.ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=fwd.device)
         self._lib = lib
         self._args = (_ptr(grad_out), _ptr(fwd.out), B, H, W, C, fwd._dt, _ptr(fwd.label),
-                      _ptr(fwd.guide), _ptr(fwd.shell), _ptr(fwd.order), _ptr(fwd.offsets), int(K),
-                      ctypes.byref(self._cp), _ptr(grad_img), _ptr(grad_guide), _ptr(self.ws),
-                      self.ws.numel())
+                      _ptr(fwd.guide), _ptr(fwd.shell), int(K), ctypes.byref(self._cp),
+                      _ptr(grad_img), _ptr(grad_guide), _ptr(self.ws), self.ws.numel())
         self.device = fwd.device
 
     def run(self, stream: torch.cuda.Stream | None = None):
@@ -398,7 +391,7 @@ class GuidefillFn(torch.autograd.Function):
     def forward(ctx, img, theta, label, params: Params):
         g = torch.stack([torch.cos(theta), torch.sin(theta)], dim=-1)
         g = torch.where((label == 1).unsqueeze(-1), g, torch.zeros_like(g)).contiguous()
-        r = fill_batched(img.contiguous(), label, g, params, record_order=True)
+        r = fill_batched(img.contiguous(), label, g, params)
         ctx.save_for_backward(theta, label, g)
         ctx.fwd = r
         ctx.params = params

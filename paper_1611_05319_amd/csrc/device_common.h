@@ -57,6 +57,7 @@ enum : int {
     G_READY = 736,  // epoch of the launch whose start-up is complete (never zeroed)
     G_LEAD = 768,   // [3] start-up leader election, ring by launch slot
     G_NX = 800,     // [kXcd] workgroups taking part per XCD group, this launch
+    G_KEND = 832,   // adjoint: largest shell + 1 in the shell map
 };
 constexpr int kLaunchSlots = 3;         // join-word sets in the ring (see launch_start)
 constexpr unsigned kClosed = 1u << 30;  // join word: the poll is closed

@@ -9,9 +9,11 @@
 // floors and lattice-line tests, the smart-order confidence) is FP64 with no
 // contraction, as the reference computes it.  The weights and the weighted
 // sum are FP64; the bilinear value of one ghost point is interpolated in FP32
-// from the stored (binary32 / binary16) colours, exact on lattice lines and
-// for constant data.
+// from binary32 colours (exact on lattice lines and for constant data) and in
+// FP64 from binary16 colours.
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -106,7 +108,10 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
     const int P = v.pitch();
     // pass 1: readable set and bilinear supports (kept for pass 2)
     constexpr int PL = per_lane<G>();
-    float fxs[PL], fys[PL];
+    // binary16 storage: the ghost values are interpolated in FP64 (see pass 2)
+    constexpr bool kF64Values = std::is_same<TS, __half>::value;
+    using FT = typename std::conditional<kF64Values, double, float>::type;
+    FT fxs[PL], fys[PL];
     int base[PL];
     unsigned rmask = 0, exmask = 0, eymask = 0;
     int n2min = 0x7fffffff;    // rotated ball: smallest readable n^2
@@ -121,8 +126,8 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
         const bool ex = (ox == fx0), ey = (oy == fy0);
         const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
         const int x1 = x0 + (ex ? 0 : 1), y1 = y0 + (ey ? 0 : 1);
-        fxs[r] = (float)(ox - fx0);
-        fys[r] = (float)(oy - fy0);
+        fxs[r] = (FT)(ox - fx0);
+        fys[r] = (FT)(oy - fy0);
         const bool ins = v.inside(x0, y0, x1, y1);
         const int b = ins ? v.index(x0, y0) : 0;
         const int dx = (ex || !ins) ? 0 : 1, dy = (ey || !ins) ? 0 : P;
@@ -212,16 +217,40 @@ __device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool g
             v.colours(i10, c10);
             v.colours(i01, c01);
             v.colours(i11, c11);
-            const float fx = fxs[r], fy = fys[r];
             // channels past C carry padding or zeros: their sums are never used,
             // so three are interpolated without a test
+            if constexpr (kF64Values) {
+                // binary16 storage: each stored value is an exact binary64, and
+                // the value is the tensor-product form sum_b sum_a bx_a by_b u
+                // in FP64 (a zero fraction adds exact zeros), so the filled
+                // value differs from an FP64 evaluation only by the order of
+                // the weighted sum; rounding to binary16 then agrees except
+                // within ~1e-16 of a rounding midpoint.  (An FP32 value here
+                // could round a fill to the neighbouring binary16 number, and
+                // later shells carry that step on.)
+                const double fx = fxs[r], fy = fys[r];
+                const double bx0 = 1.0 - fx, by0 = 1.0 - fy;
+                const double b00 = bx0 * by0, b10 = fx * by0, b01 = bx0 * fy, b11 = fx * fy;
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                if (ch < 3 || C == 4) {
-                    const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
-                    const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
-                    const float val = fmaf(fy, bot - top, top);
-                    acc[ch] = fma(w, (double)val, acc[ch]);
+                for (int ch = 0; ch < 4; ++ch) {
+                    if (ch < 3 || C == 4) {
+                        double val = b00 * (double)c00[ch];
+                        val = val + b10 * (double)c10[ch];
+                        val = val + b01 * (double)c01[ch];
+                        val = val + b11 * (double)c11[ch];
+                        acc[ch] = fma(w, val, acc[ch]);
+                    }
+                }
+            } else {
+                const float fx = fxs[r], fy = fys[r];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    if (ch < 3 || C == 4) {
+                        const float top = fmaf(fx, c10[ch] - c00[ch], c00[ch]);
+                        const float bot = fmaf(fx, c11[ch] - c01[ch], c01[ch]);
+                        const float val = fmaf(fy, bot - top, top);
+                        acc[ch] = fma(w, (double)val, acc[ch]);
+                    }
                 }
             }
         }

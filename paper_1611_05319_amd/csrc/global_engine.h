@@ -38,7 +38,6 @@ struct FillArgs {
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
 constexpr int kAggMaxD = 4;    // adjoint: support patches up to (2*4+1)^2 pixels in LDS
-constexpr int kAggPatch = (2 * kAggMaxD + 1) * (2 * kAggMaxD + 1) * 4;  // floats per group
 
 // LDS staging of list appends: one global atomic per workgroup per flush
 struct Stage {
@@ -474,27 +473,53 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
 }
 
 // ---------------------------------------------------------------------------
-// reverse shells over a recorded fill order
+// reverse shells, grouped from the shell map
+
+constexpr int kBwdBins = 2048;  // shells counted per round of the counting sort (LDS bins)
 
 struct BwdArgs {
     const float *grad_out;
     const void *img;
     const float *guide;
     const int32_t *shell;
-    const int32_t *order;
-    const int32_t *shell_off;
     float *grad_img;
     float *grad_guide;
     int32_t *ctl;
+    int32_t *gcount;  // [2][kBwdBins]: pixels per shell of a sorting round (two buffers)
+    int32_t *offs;    // start of shell k in order; entry K its end
+    int32_t *order;   // [NP] filled pixels grouped by shell
     long long HW;
     long long NP;
-    int B, H, W, C, K;
+    int B, H, W, C, K;  // K < 0: replay every shell of the map (max s + 1)
     int aliased;
     double eps;
     double a;
     int ghost;
     LaunchSync sync;  // launch start-up (join words and epoch)
 };
+
+// exclusive prefix sum of v over the workgroup (kBlock threads); *total gets the sum
+__device__ inline int block_exclusive_scan(int v, int *s_wave, int *total) {
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wv] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int t = s_wave[w];
+        before += w < wv ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+}
 
 // Adjoint of one filled pixel x (shell k), one pass over its ball:
 //   u = (1/S) sum_j w_j v_j,  S = sum_j w_j,  log w_j = -a (g_perp . o_j)^2 - log|o_j|
@@ -503,6 +528,7 @@ struct BwdArgs {
 // so every sum is accumulated in the same pass as S and u; |o_j| does not
 // depend on g (the rotation preserves length).  A second pass scatters
 // ubar(x) w_j / S times the bilinear basis values into the support pixels.
+// agg: this group's LDS patch of (2D + 1)^2 pixels x C floats, or nullptr.
 template <typename TS, int G>
 __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rinv, int T,
                           long long gidx, float2 gv, int k, int l, float *agg, int D) {
@@ -510,6 +536,13 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
     const int W = A.W;
+    const int C = A.C;
+    float *GI = A.grad_img;
+    // the adjoint arriving at x is complete: every shell after k is done
+    double ub[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < C) ub[ch] = (double)GI[gidx * C + ch];
     const int32_t *S = A.shell + f * A.HW;
     const double gx = (double)gv.x, gy = (double)gv.y;
     const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
@@ -519,7 +552,6 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
         cs = gx / L;
         sn = gy / L;
     }
-    const int C = A.C;
     const TS *U = reinterpret_cast<const TS *>(A.img) + f * A.HW * C;
     // pass 1: geometry and readable set (kept for the other passes)
     double fxs[kPerLaneMax], fys[kPerLaneMax], q[kPerLaneMax];
@@ -617,13 +649,10 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     Bx = gsum<G>(Bx);
     By = gsum<G>(By);
     const double inv = 1.0 / Ssum;
-    float *GI = A.grad_img;
-    double ub[4] = {0.0, 0.0, 0.0, 0.0};
     double dgx = 0.0, dgy = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
         if (ch < C) {
-            ub[ch] = (double)GI[gidx * C + ch];
             const double u = gsum<G>(Uc[ch]) * inv;
             dgx += ub[ch] * (gsum<G>(Ax[ch]) - u * Bx + gsum<G>(Dx[ch])) * inv;
             dgy += ub[ch] * (gsum<G>(Ay[ch]) - u * By + gsum<G>(Dy[ch])) * inv;
@@ -701,39 +730,113 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     }
 }
 
+// Bytes of dynamic LDS the adjoint launch takes: the sorting bins, later the
+// groups' support patches
+__host__ __device__ inline size_t bwd_dyn_lds(int G, int D, int C) {
+    const size_t bins = 2 * (size_t)kBwdBins * sizeof(int);
+    const size_t patches = D <= kAggMaxD ? (size_t)(kBlock / G) * (2 * D + 1) * (2 * D + 1) * C * sizeof(float) : 0;
+    return bins > patches ? bins : patches;
+}
+
+// One persistent launch: (1) group the filled pixels by shell with a counting
+// sort over the shell map (per-workgroup LDS histograms, one global atomic per
+// workgroup and shell, prefix sums), in the same sweep that passes grad_out
+// through to grad_img and clears grad_guide; (2) replay the shells from the
+// last to the first, one grid barrier apart.
 template <typename TS, int G>
-__global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
+__global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
     __shared__ int s_T;
     __shared__ int s_item[kItemCap];
     __shared__ float2 s_gd[kItemCap];
-    __shared__ float s_agg[(kBlock / G) * kAggPatch];  // one support patch per group
+    __shared__ int s_wave[kBlock / 64];
+    __shared__ int s_kend;  // max s + 1 over this workgroup's pixels
     const int tid = threadIdx.x;
     GridInfo grid;
-    if (!launch_start(A.ctl, A.sync, grid, nullptr, 0, nullptr, 0, nullptr, 0)) return;
+    if (!launch_start(A.ctl, A.sync, grid, A.gcount, 2 * kBwdBins, nullptr, 0, nullptr, 0)) return;
     const int nblk = grid.n, lw = grid.lw;
     build_offsets(A.eps, s_off, s_rinv, &s_T);
-    __syncthreads();
-    const int T = s_T;
-    {
-        // grad_img = grad_out, grad_guide = 0
-        const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
-        if (!A.aliased)
-            for (long long i = lo * A.C + tid; i < hi * A.C; i += kBlock) A.grad_img[i] = A.grad_out[i];
-        for (long long i = lo * 2 + tid; i < hi * 2; i += kBlock) A.grad_guide[i] = 0.0f;
+    const int C = A.C;
+    int *s_bin = reinterpret_cast<int *>(smem);  // per shell: count, then this workgroup's next slot
+    int *s_boff = s_bin + kBwdBins;              // per shell: start in order
+    // ---- counting sort of the filled pixels by shell -------------------------
+    const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
+    int K = A.K;
+    int first = 0;  // order position of the round's first shell
+    for (int c = 0;; ++c) {
+        const int cb = c * kBwdBins;
+        int32_t *gcnt = A.gcount + (c & 1) * kBwdBins;
+        for (int i = tid; i < kBwdBins; i += kBlock) s_bin[i] = 0;
+        if (tid == 0) s_kend = 0;
+        __syncthreads();
+        int kend = 0;
+        for (long long p = lo + tid; p < hi; p += kBlock) {
+            const int s = A.shell[p];
+            if (c == 0) {  // gradient of the output passes through; guide gradient 0
+                if (!A.aliased)
+                    for (int ch = 0; ch < C; ++ch) A.grad_img[p * C + ch] = A.grad_out[p * C + ch];
+                A.grad_guide[2 * p] = 0.0f;
+                A.grad_guide[2 * p + 1] = 0.0f;
+                kend = max(kend, s + 1);
+            }
+            const int kk = s - cb;
+            if (s >= 0 && (K < 0 || s < K) && kk < kBwdBins && kk >= 0) atomicAdd(&s_bin[kk], 1);
+        }
+        if (c == 0) wave_max(kend, &s_kend);
+        __syncthreads();
+        for (int i = tid; i < kBwdBins; i += kBlock) {  // reserve this workgroup's slots per shell
+            const int n = s_bin[i];
+            s_bin[i] = n ? atomicAdd(&gcnt[i], n) : 0;
+        }
+        if (c == 0 && tid == 0 && s_kend > 0) atomicMax(&A.ctl[G_KEND], s_kend);
+        grid_sync(A.ctl, grid);
+        if (c == 0 && K < 0) K = ld_ctl(A.ctl, G_KEND);
+        const int nb = min(kBwdBins, K - cb);  // shells of this round
+        int run = first;
+        for (int b0 = 0; b0 < nb; b0 += kBlock) {
+            const int i = b0 + tid;
+            const int v = i < nb ? ld_ctl(gcnt, i) : 0;
+            int tot = 0;
+            const int ex = block_exclusive_scan(v, s_wave, &tot);
+            if (i < nb) {
+                s_boff[i] = run + ex;
+                if (lw == 0) A.offs[cb + i] = run + ex;
+            }
+            run += tot;
+        }
+        if (lw == 0 && tid == 0 && cb + kBwdBins >= K) A.offs[K > 0 ? K : 0] = run;
+        __syncthreads();
+        for (long long p = lo + tid; p < hi; p += kBlock) {
+            const int s = A.shell[p];
+            const int kk = s - cb;
+            if (s >= 0 && s < K && kk >= 0 && kk < nb) {
+                const int slot = atomicAdd(&s_bin[kk], 1);
+                A.order[s_boff[kk] + slot] = (int)p;
+            }
+        }
+        // the other count buffer was last read before the previous barrier
+        if (lw == 0)
+            for (int i = tid; i < kBwdBins; i += kBlock) A.gcount[((c + 1) & 1) * kBwdBins + i] = 0;
+        first = run;
+        grid_sync(A.ctl, grid);
+        if (cb + kBwdBins >= K) break;
     }
-    grid_sync(A.ctl, grid);
+    // ---- reverse shells ---------------------------------------------------------
+    const int T = s_T;
     const int nG = kBlock / G;
     const int gi = tid / G, l = tid & (G - 1);
     const int D = (int)ceil(A.eps);
-    const bool use_agg = D <= kAggMaxD && G <= 64;
-    for (int k = A.K - 1; k >= 0; --k) {
-        const long long b0 = A.shell_off[k], b1 = A.shell_off[k + 1];
+    const bool use_agg = D <= kAggMaxD;
+    const int patch = (2 * D + 1) * (2 * D + 1) * C;
+    float *agg = reinterpret_cast<float *>(smem) + gi * patch;
+    for (int k = K - 1; k >= 0; --k) {
+        const long long b0 = ld_ctl(A.offs, k), b1 = ld_ctl(A.offs, k + 1);
         const long long n = b1 - b0;
-        const long long lo = b0 + n * lw / nblk, hi = b0 + n * (lw + 1) / nblk;
-        for (long long c0 = lo; c0 < hi; c0 += kItemCap) {  // items and guides via LDS
-            const int cn = (int)min((long long)kItemCap, hi - c0);
+        const long long lo2 = b0 + n * lw / nblk, hi2 = b0 + n * (lw + 1) / nblk;
+        for (long long c0 = lo2; c0 < hi2; c0 += kItemCap) {  // items and guides via LDS
+            const int cn = (int)min((long long)kItemCap, hi2 - c0);
             __syncthreads();
             for (int i = tid; i < cn; i += kBlock) {
                 const int gidx = A.order[c0 + i];
@@ -745,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(BwdArgs A) {
                 const int item = base + gi;
                 if (item < cn)
                     bwd_pixel<TS, G>(A, s_off, s_rinv, T, s_item[item], s_gd[item], k, l,
-                                     use_agg ? s_agg + gi * kAggPatch : nullptr, D);
+                                     use_agg ? agg : nullptr, D);
             }
         }
         grid_sync(A.ctl, grid);

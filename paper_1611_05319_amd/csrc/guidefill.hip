@@ -11,10 +11,12 @@
 // device holds); at start-up the resident workgroups join, one of them zeroes
 // the control words and the stats while the others wait for it.
 //
-// All arithmetic of the fill is FP64: the ghost offsets must be bit-identical
+// Every decision of the fill is FP64: the ghost offsets must be bit-identical
 // to the reference (points that land on lattice lines change the readable
 // set), so the rotation is evaluated as ox = n*s + m*c, oy = m*s - n*c with
 // (c, s) = g/|g|, IEEE division and square root, and no contraction into FMA.
+// The weights and weighted sums are FP64 too; each ghost value is
+// interpolated in FP32 from the stored colours.
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -129,7 +131,17 @@ void commit_launch(const void *ws, const LaunchSync &ls) {
     g_launch_states[ws] = LaunchState{ls.epoch, ls.slot};
 }
 
-gf_status validate(const gf_params *p, int B, int H, int W, int C, gf_dtype dt) {
+// The raw value of an enum argument: C callers may pass any int, and loading
+// an out-of-range value through the C++ enum type would be undefined, so the
+// bits are copied into an int and compared as such.
+template <typename E> int raw_enum(const E *v) {
+    static_assert(sizeof(E) == sizeof(int), "enum arguments are int-sized");
+    int r;
+    memcpy(&r, v, sizeof r);
+    return r;
+}
+
+gf_status validate(const gf_params *p, int B, int H, int W, int C, int dt) {
     if (!p) return GF_EINVAL;
     if (B < 1 || H < 1 || W < 1 || C < 1 || C > 4) return GF_EINVAL;
     if (dt != GF_F32 && dt != GF_F16) return GF_EINVAL;
@@ -302,10 +314,29 @@ gf_status run_tiled(const TileArgs &A, int G, int NT, int bpc, size_t lds, hipSt
 template <typename TS>
 gf_status run_bwd(const BwdArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
-    if (G == 8) return launch_persistent(bwd_kernel<TS, 8>, &A, bpc, mb, 0, s);
-    if (G == 16) return launch_persistent(bwd_kernel<TS, 16>, &A, bpc, mb, 0, s);
-    if (G == 32) return launch_persistent(bwd_kernel<TS, 32>, &A, bpc, mb, 0, s);
-    return launch_persistent(bwd_kernel<TS, 64>, &A, bpc, mb, 0, s);
+    if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers and LDS allow
+    const size_t lds = bwd_dyn_lds(G, (int)ceil(A.eps), A.C);
+    if (G == 8) return launch_persistent(bwd_kernel<TS, 8>, &A, bpc, mb, lds, s);
+    if (G == 16) return launch_persistent(bwd_kernel<TS, 16>, &A, bpc, mb, lds, s);
+    if (G == 32) return launch_persistent(bwd_kernel<TS, 32>, &A, bpc, mb, lds, s);
+    return launch_persistent(bwd_kernel<TS, 64>, &A, bpc, mb, lds, s);
+}
+
+// adjoint workspace: control block, two rounds of shell counts, shell offsets
+// (a frame has at most H * W shells), the filled pixels grouped by shell
+struct BwdLayout {
+    size_t ctl, gcount, offs, order, total;
+};
+
+BwdLayout bwd_layout(int B, int H, int W) {
+    BwdLayout L;
+    size_t off = 0;
+    L.ctl = off; off += align256(kCtlWords * sizeof(int32_t));
+    L.gcount = off; off += align256(2 * (size_t)kBwdBins * sizeof(int32_t));
+    L.offs = off; off += align256(((size_t)H * W + 2) * sizeof(int32_t));
+    L.order = off; off += align256((size_t)B * H * W * sizeof(int32_t));
+    L.total = off;
+    return L;
 }
 
 struct WsLayout {
@@ -314,7 +345,7 @@ struct WsLayout {
     size_t total;
 };
 
-bool layout_for(int B, int H, int W, int C, gf_dtype dt, const gf_params *p, WsLayout &L,
+bool layout_for(int B, int H, int W, int C, int dt, const gf_params *p, WsLayout &L,
                 TileGeom *geom_out, int *tiles_x, int *tiles_y) {
     memset(&L, 0, sizeof L);
     size_t off = align256(kCtlWords * sizeof(int32_t));
@@ -351,6 +382,19 @@ bool layout_for(int B, int H, int W, int C, gf_dtype dt, const gf_params *p, WsL
     return true;
 }
 
+size_t workspace_bytes(int B, int H, int W, int C, int dt, const gf_params *p) {
+    if (!p || B < 1 || H < 1 || W < 1 || C < 1 || (dt != GF_F32 && dt != GF_F16)) return 0;
+    WsLayout L;
+    if (!layout_for(B, H, W, C, dt, p, L, nullptr, nullptr, nullptr)) return 0;
+    return L.total;
+}
+
+gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, int C, int dt,
+                       const uint8_t *label, const float *guide, const gf_params *p,
+                       int32_t *shell_out, int32_t *stats, int32_t *order_out,
+                       int32_t *shell_offsets, int32_t *front_hist, int kcap, void *workspace,
+                       size_t ws_bytes, void *stream);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -358,10 +402,10 @@ bool layout_for(int B, int H, int W, int C, gf_dtype dt, const gf_params *p, WsL
 
 extern "C" {
 
-int gf_version(void) { return 1; }
+int gf_version(void) { return 2; }
 
-const char *gf_status_string(gf_status s) {
-    switch (s) {
+const char *gf_status_string(gf_status s_arg) {
+    switch (raw_enum(&s_arg)) {
     case GF_OK: return "ok";
     case GF_EINVAL: return "invalid argument";
     case GF_EDEVICE: return "HIP device error";
@@ -373,15 +417,13 @@ const char *gf_status_string(gf_status s) {
 const char *gf_last_error(void) { return g_last_error; }
 
 size_t gf_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p) {
-    if (!p || B < 1 || H < 1 || W < 1 || C < 1) return 0;
-    WsLayout L;
-    if (!layout_for(B, H, W, C, dt, p, L, nullptr, nullptr, nullptr)) return 0;
-    return L.total;
+    return workspace_bytes(B, H, W, C, raw_enum(&dt), p);
 }
 
 size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p) {
-    (void)B; (void)H; (void)W; (void)C; (void)dt; (void)p;
-    return align256(kCtlWords * sizeof(int32_t));
+    (void)C; (void)dt; (void)p;
+    if (B < 1 || H < 1 || W < 1) return 0;
+    return bwd_layout(B, H, W).total;
 }
 
 gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W, int C,
@@ -389,6 +431,20 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
                           const gf_params *p, int32_t *shell_out, int32_t *stats,
                           int32_t *order_out, int32_t *shell_offsets, int32_t *front_hist,
                           int kcap, void *workspace, size_t ws_bytes, void *stream) {
+    return fill_batched(img_in, img_out, B, H, W, C, raw_enum(&dt), label, guide, p, shell_out,
+                        stats, order_out, shell_offsets, front_hist, kcap, workspace, ws_bytes,
+                        stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, int C, int dt,
+                       const uint8_t *label, const float *guide, const gf_params *p,
+                       int32_t *shell_out, int32_t *stats, int32_t *order_out,
+                       int32_t *shell_offsets, int32_t *front_hist, int kcap, void *workspace,
+                       size_t ws_bytes, void *stream) {
     gf_status st = validate(p, B, H, W, C, dt);
     if (st != GF_OK) return st;
     if (!img_in || !img_out || !label || !guide || !shell_out || !stats || !workspace)
@@ -494,16 +550,22 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
     return rc;
 }
 
+}  // namespace
+
+extern "C" {
+
 gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,
                   const uint8_t *label, const float *guide, const gf_params *p,
                   int32_t *shell_out, int32_t *stats, void *workspace, size_t ws_bytes,
                   void *stream) {
-    return gf_fill_batched(img_in, img_out, 1, H, W, C, dt, label, guide, p, shell_out, stats,
-                           nullptr, nullptr, nullptr, 0, workspace, ws_bytes, stream);
+    return fill_batched(img_in, img_out, 1, H, W, C, raw_enum(&dt), label, guide, p, shell_out,
+                        stats, nullptr, nullptr, nullptr, 0, workspace, ws_bytes, stream);
 }
 
-gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p, int32_t *out6) {
-    if (!p || !out6 || H < 1 || W < 1 || C < 1 || C > 4) return GF_EINVAL;
+gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt_arg, const gf_params *p, int32_t *out6) {
+    const int dt = raw_enum(&dt_arg);
+    if (!p || !out6 || H < 1 || W < 1 || C < 1 || C > 4 || (dt != GF_F32 && dt != GF_F16))
+        return GF_EINVAL;
     int dev = 0;
     size_t lds_limit = 65536;
     if (hipGetDevice(&dev) == hipSuccess) lds_limit = device_info(dev).lds_block;
@@ -521,18 +583,17 @@ gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p,
 }
 
 gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, int H, int W, int C,
-                           gf_dtype dt, const uint8_t *label, const float *guide,
-                           const int32_t *shell, const int32_t *order,
-                           const int32_t *shell_offsets, int K, const gf_params *p,
-                           float *grad_img, float *grad_guide, void *workspace,
-                           size_t ws_bytes, void *stream) {
-    (void)label;
+                           gf_dtype dt_arg, const uint8_t *label, const float *guide,
+                           const int32_t *shell, int K, const gf_params *p, float *grad_img,
+                           float *grad_guide, void *workspace, size_t ws_bytes, void *stream) {
+    (void)label;  // the shell map carries every role the adjoint needs
+    const int dt = raw_enum(&dt_arg);
     gf_status st = validate(p, B, H, W, C, dt);
     if (st != GF_OK) return st;
-    if (!grad_out || !img_out || !guide || !shell || !order || !shell_offsets || !grad_img ||
-        !grad_guide || !workspace || K < 0)
+    if (!grad_out || !img_out || !guide || !shell || !grad_img || !grad_guide || !workspace)
         return GF_EINVAL;
-    if (ws_bytes < gf_backward_workspace_size(B, H, W, C, dt, p)) return GF_EINVAL;
+    if (K < -1 || (long long)K > (long long)H * W) return GF_EINVAL;
+    if (ws_bytes < bwd_layout(B, H, W).total) return GF_EINVAL;
     if (((uintptr_t)workspace & 255) != 0) return GF_EINVAL;
     gf_params q = *p;
     q.engine = GF_ENGINE_FRONT;
@@ -544,16 +605,19 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
     }
     if (T > G * kPerLaneMax || T > kMaxOffsets) return GF_EUNSUPPORTED;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const BwdLayout L = bwd_layout(B, H, W);
+    char *ws = reinterpret_cast<char *>(workspace);
     BwdArgs A;
     A.grad_out = grad_out;
     A.img = img_out;
     A.guide = guide;
     A.shell = shell;
-    A.order = order;
-    A.shell_off = shell_offsets;
     A.grad_img = grad_img;
     A.grad_guide = grad_guide;
-    A.ctl = reinterpret_cast<int32_t *>(workspace);
+    A.ctl = reinterpret_cast<int32_t *>(ws + L.ctl);
+    A.gcount = reinterpret_cast<int32_t *>(ws + L.gcount);
+    A.offs = reinterpret_cast<int32_t *>(ws + L.offs);
+    A.order = reinterpret_cast<int32_t *>(ws + L.order);
     A.HW = (long long)H * W;
     A.NP = (long long)B * H * W;
     A.B = B;

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.gf_version() == 1
+    assert lib.gf_version() == 2
     assert lib.gf_status_string(0) == b"ok"
     assert lib.gf_status_string(-1) == b"invalid argument"
     assert lib.gf_status_string(-2) == b"HIP device error"
@@ -157,12 +157,21 @@ def test_backward_rejects_bad_arguments(lib):
     P = ctypes.c_void_p
     fake = P(1 << 20)
     p = gf.Params().c_struct()
-    rc = lib.gf_fill_backward(fake, fake, 1, 8, 8, 3, 0, fake, fake, fake, None, fake, 2,
-                              ctypes.byref(p), fake, fake, fake, 1 << 20, None)
-    assert rc == -1
-    rc = lib.gf_fill_backward(fake, fake, 1, 8, 8, 3, 0, fake, fake, fake, fake, fake, -1,
-                              ctypes.byref(p), fake, fake, fake, 1 << 20, None)
-    assert rc == -1
+    nbytes = lib.gf_backward_workspace_size(1, 8, 8, 3, 0, ctypes.byref(p))
+    # control block, shell counts, H * W + 2 shell offsets, B * H * W order entries
+    assert nbytes >= 4096 + 2 * 2048 * 4 + (64 + 2) * 4 + 64 * 4 and nbytes % 256 == 0
+
+    def call(shell=fake, K=2, ws_bytes=nbytes, ws=fake, grad=fake, params=p):
+        return lib.gf_fill_backward(grad, fake, 1, 8, 8, 3, 0, None, fake, shell, K,
+                                    ctypes.byref(params), fake, fake, ws, ws_bytes, None)
+
+    assert call(shell=None) == -1              # no shell map
+    assert call(grad=None) == -1               # no grad_out
+    assert call(K=-2) == -1                    # K below -1
+    assert call(K=65) == -1                    # more shells than pixels in a frame
+    assert call(ws_bytes=nbytes - 256) == -1   # workspace too small
+    assert call(ws=P((1 << 20) + 8)) == -1     # misaligned workspace
+    assert call(params=gf.Params(eps=0.5).c_struct()) == -1
 
 
 def test_python_binding_fails_loudly_without_device():
@@ -177,3 +186,4 @@ def test_python_binding_fails_loudly_without_device():
     g = torch.zeros(4, 4, 2)
     with pytest.raises(ValueError):
         gf.fill(img, lab, g)
+

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synthetic as syn
-from gpu_helpers import banner, gpu_fill, to_dev
+from gpu_helpers import assert_colour_parity, banner, gpu_fill, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _frames(B, H, W, seed=5):
     return np.stack(imgs), lab, g, th
 
 
-def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0):
+def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0, engine=0):
     import torch
 
     import paper_1611_05319_amd as gf
@@ -42,15 +42,18 @@ def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0):
     img, lab, g, th = _frames(B, H, W)
     rng = np.random.default_rng(77)
     omega = rng.normal(size=img.shape).astype(np.float32)
-    u, s, st, r = gpu_fill(img, lab, g, record_order=True, ghost=ghost, mu=mu, eps=eps)
+    u, s, st, r = gpu_fill(img, lab, g, ghost=ghost, mu=mu, eps=eps, engine=engine)
     gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g),
                               gf.Params(eps=eps, mu=mu, ghost=ghost))
     torch.cuda.synchronize()
     gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
     ref = oracle.fill(img, lab, g, eps=eps, mu=mu, ghost=ghost)
     np.testing.assert_array_equal(s, ref.shell)
-    # the oracle adjoint evaluated at the GPU's forward output (binary32 colours)
-    ri, rg = oracle.adjoint(lab, g, u, s, omega.astype(np.float64), eps=eps, mu=mu, ghost=ghost)
+    worst = assert_colour_parity(u, ref.u, ref.shell)
+    banner(f"forward: K={st['K']} worst rel colour err {worst:.2e}")
+    # the oracle adjoint at the oracle's own forward (nothing taken from the HIP path)
+    ri, rg = oracle.adjoint(lab, g, ref.u, ref.shell, omega.astype(np.float64), eps=eps, mu=mu,
+                            ghost=ghost)
     for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
         err = np.abs(a - b)
         rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
@@ -67,10 +70,42 @@ def test_adjoint_small(ghost, eps):
     _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0, eps=eps)
 
 
-def test_adjoint_config5_full():
-    banner("adjoint 16 x 512 x 512")
-    st = _compare(16, 512, 512)
+@pytest.mark.parametrize("engine", [0, 1])
+def test_adjoint_config5_full(engine):
+    banner(f"adjoint 16 x 512 x 512, forward engine {engine}")
+    st = _compare(16, 512, 512, engine=engine)
     assert st["K"] >= 3
+
+
+def test_adjoint_replays_given_shell_count():
+    """K passed explicitly (the forward's statistic) equals K taken from the
+    map; a smaller K is the adjoint of a fill stopped after K shells."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner("adjoint with explicit K")
+    img, lab, g, th = _frames(2, 80, 96, seed=9)
+    omega = np.random.default_rng(78).normal(size=img.shape).astype(np.float32)
+    u, s, st, r = gpu_fill(img, lab, g)
+    K = st["K"]
+    assert K >= 4
+    dev_args = (to_dev(omega), r, to_dev(lab), to_dev(g), gf.Params())
+    gi_a, gg_a = gf.fill_backward(*dev_args)
+    gi_b, gg_b = gf.fill_backward(*dev_args, K=K)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(gi_b.cpu().numpy(), gi_a.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(gg_b.cpu().numpy(), gg_a.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    # replaying K - 2 shells = the adjoint of the fill stopped after K - 2 shells
+    m = K - 2
+    u2, s2, st2, r2 = gpu_fill(img, lab, g, max_shells=m)
+    gi_c, gg_c = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g), gf.Params(), K=m)
+    torch.cuda.synchronize()
+    ref = oracle.fill(img, lab, g, max_shells=m)
+    np.testing.assert_array_equal(s2, ref.shell)
+    ri, rg = oracle.adjoint(lab, g, ref.u, ref.shell, omega.astype(np.float64))
+    assert np.abs(gi_c.cpu().numpy() - ri).max() <= 1e-4
+    assert np.abs(gg_c.cpu().numpy() - rg).max() <= 1e-4
 
 
 def test_autograd_function():
@@ -87,12 +122,14 @@ def test_autograd_function():
     rng = np.random.default_rng(3)
     omega = to_dev(rng.normal(size=img.shape).astype(np.float32))
     (out * omega).sum().backward()
-    # reference: oracle adjoint at the GPU forward, chained to theta
-    u = out.detach().cpu().numpy().astype(np.float64)
-    s = shell.cpu().numpy()
+    # reference: the oracle's forward and adjoint, chained to theta; g is formed
+    # in float32 as the autograd function forms it
     gnp = np.stack([np.cos(th), np.sin(th)], -1).astype(np.float32)
     gnp = np.where((lab == 1)[..., None], gnp, np.float32(0))
-    ri, rg = oracle.adjoint(lab, gnp, u, s, omega.cpu().numpy().astype(np.float64))
+    ref = oracle.fill(img, lab, gnp)
+    np.testing.assert_array_equal(shell.cpu().numpy(), ref.shell)
+    assert_colour_parity(out.detach().cpu().numpy().astype(np.float64), ref.u, ref.shell)
+    ri, rg = oracle.adjoint(lab, gnp, ref.u, ref.shell, omega.cpu().numpy().astype(np.float64))
     rth = -np.sin(th) * rg[..., 0] + np.cos(th) * rg[..., 1]
     rth = np.where(lab == 1, rth, 0.0)
     assert np.abs(timg.grad.cpu().numpy() - ri).max() <= 1e-4

@@ -159,10 +159,11 @@ FORMS = [
     {"engine": 1, "inplace": True}, {"group": 8}, {"group": 16}, {"group": 32}, {"group": 64},
     {"engine": 1, "group": 16}, {"blocks_per_cu": 1}, {"blocks_per_cu": 4},
     {"tile_w": 12, "tile_h": 12, "pass_shells": 1}, {"tile_w": 16, "tile_h": 24, "pass_shells": 2},
-    {"tile_w": 40, "tile_h": 40, "pass_shells": 8}, {"tile_w": 24, "tile_h": 24, "pass_shells": 6},
+    {"tile_w": 24, "tile_h": 24, "pass_shells": 6},
     {"tile_w": 64, "tile_h": 16, "pass_shells": 5}, {"tile_w": 20, "tile_h": 36, "pass_shells": 3},
-    {"tile_w": 24, "tile_h": 24, "pass_shells": 8, "tracking": False},
-    {"tile_w": 100, "tile_h": 120, "pass_shells": 2},
+    {"tile_w": 24, "tile_h": 24, "pass_shells": 7, "tracking": False},
+    {"tile_w": 48, "tile_h": 48, "pass_shells": 2}, {"tile_w": 20, "tile_h": 20, "pass_shells": 6},
+    {"tile_w": 27, "tile_h": 27, "pass_shells": 7},
     {"tile_threads": 256}, {"tile_threads": 512}, {"tile_threads": 512, "pass_shells": 2},
     {"group": 4}, {"group": 4, "tile_threads": 512}, {"group": 4, "tracking": False},
     {"tile_threads": 768}, {"tile_threads": 768, "group": 16, "pass_shells": 3},
@@ -183,13 +184,6 @@ def test_forms_agree_exactly():
     import paper_1611_05319_amd as gf
 
     for kw in FORMS:
-        if "tile_w" in kw:
-            try:  # windows larger than the device's LDS per workgroup are rejected
-                gf.tile_geometry(200, 240, 3, params=gf.Params(**{k: v for k, v in kw.items()
-                                                                  if k != "inplace"}))
-            except RuntimeError:
-                banner(f"form {kw}: window does not fit, skipped")
-                continue
         banner(f"form {kw}")
         u1, s1, st1, _ = gpu_fill(img, lab, g, **kw)
         np.testing.assert_array_equal(s1, s0)
@@ -213,6 +207,60 @@ def test_forms_agree_exactly():
             np.testing.assert_array_equal(ub[i], ui)
             assert stb["frame_K"][i] == sti["K"] and stb["frame_filled"][i] == sti["filled"]
             assert stb["frame_hole"][i] == sti["hole"]
+
+
+# windows that do not fit: more than 8192 window pixels (uint16 local lists),
+# or more LDS than one workgroup may use (32 bytes per window pixel)
+OVERSIZE = [{"tile_w": 100, "tile_h": 120, "pass_shells": 2}, {"tile_w": 40, "tile_h": 40, "pass_shells": 8},
+            {"tile_w": 24, "tile_h": 24, "pass_shells": 8}]
+
+
+@pytest.mark.parametrize("kw", OVERSIZE)
+def test_oversize_windows_are_rejected(kw):
+    import paper_1611_05319_amd as gf
+
+    banner(f"oversize window {kw}")
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        gf.tile_geometry(200, 240, 3, params=gf.Params(**kw))
+    w = syn.config1(seed=11, H=200, W=240)
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        gpu_fill(w.image[0], w.label[0], w.guide[0], **kw)
+
+
+def test_single_frame_entry_point():
+    """gf_fill (one frame) called directly through the C ABI."""
+    import ctypes
+
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    lib = gf.load()
+    w = syn.config1(seed=13, H=180, W=220)
+    img, lab, g = w.image[0], w.label[0], w.guide[0]
+    ref = oracle.fill(img, lab, g)
+    dev = torch.device("cuda:0")
+    for engine in (0, 1):
+        banner(f"gf_fill engine={engine}")
+        ti, tl, tg = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (img, lab, g))
+        out = torch.empty_like(ti)
+        shell = torch.empty(lab.shape, dtype=torch.int32, device=dev)
+        stats = torch.empty(12, dtype=torch.int32, device=dev)
+        cp = gf.Params(engine=engine).c_struct()
+        nbytes = lib.gf_workspace_size(1, *lab.shape, 3, 0, ctypes.byref(cp))
+        ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        P = ctypes.c_void_p
+        rc = lib.gf_fill(P(ti.data_ptr()), P(out.data_ptr()), lab.shape[0], lab.shape[1], 3, 0,
+                         P(tl.data_ptr()), P(tg.data_ptr()), ctypes.byref(cp), P(shell.data_ptr()),
+                         P(stats.data_ptr()), P(ws.data_ptr()), nbytes,
+                         P(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0, lib.gf_last_error()
+        torch.cuda.synchronize()
+        s = shell.cpu().numpy()
+        np.testing.assert_array_equal(s, ref.shell)
+        assert_colour_parity(out.cpu().numpy().astype(np.float64), ref.u, ref.shell)
+        st = gf.stats_fields(stats)
+        assert st["K"] == ref.K and st["filled"] == ref.n_filled and not st["sync_timeout"]
 
 
 def test_front_sizes_match_active_boundary():
@@ -281,6 +329,23 @@ def test_config2_full_size():
             banner(f"c2 K={st['K']} N={st['filled']} worst rel err {worst:.2e}")
 
 
+@pytest.mark.parametrize("config", ["c1", "c2"])
+def test_smart_order_full_size(config):
+    """Smart order (eqn:ready, c = 0.05) on the 256x256 and 1920x1080 frames:
+    the oracle reports no confidence within its tie band of the threshold, so
+    the shell maps must agree bit for bit."""
+    w = syn.config1() if config == "c1" else syn.config2()
+    img, lab, g = w.image[0], w.label[0], w.guide[0]
+    ref = oracle.fill(img, lab, g, eps=w.eps, mu=w.mu, c=0.05)
+    assert ref.n_ties == 0, "confidence within the tie band of the threshold"
+    for engine in ENGINES:
+        for tracking in (True, False):
+            banner(f"smart order {config} c=0.05 engine={engine} tracking={tracking}")
+            ref, u, s, st, worst = _check(img, lab, g, eps=w.eps, mu=w.mu, c=0.05, tracking=tracking,
+                                          ref=ref, **LAUNCH[engine])
+            banner(f"smart order {config}: K={st['K']} worst rel err {worst:.2e}")
+
+
 def test_config3_full_size():
     w = syn.config3()
     ref = oracle.fill(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0)
@@ -292,21 +357,70 @@ def test_config3_full_size():
         assert st["K"] > 50
 
 
-def test_config4_batched_sampled():
+@pytest.fixture(scope="module")
+def config4_reference():
+    """The 64-frame binary16 batch and the oracle's fill of every frame
+    (binary16 rounding of inputs and of each fill)."""
+    banner("c4 64 x 1920x1080 fp16: generate")
+    w = syn.config4()
+    refs = []
+    for f in range(w.image.shape[0]):
+        r = oracle.fill(w.image[f].astype(np.float64), w.label[f], w.guide[f], storage="f16")
+        refs.append((r.shell, r.u.astype(np.float16), r.K, r.n_filled))
+    banner("c4 oracle done")
+    return w, refs
+
+
+def _config4_launch(name, w):
     import torch
 
-    banner("c4 64 x 1920x1080 fp16 (generate)")
-    w = syn.config4()
-    banner("c4 fill")
-    u, s, st, _ = gpu_fill(w.image.astype(np.float32), w.label, w.guide, dtype=torch.float16)
-    for f in (0, 17, 42, 63):
-        banner(f"c4 frame {f} vs oracle")
-        ref = oracle.fill(w.image[f].astype(np.float64), w.label[f], w.guide[f], storage="f16")
-        np.testing.assert_array_equal(s[f], ref.shell)
-        filled = ref.shell >= 0
-        ulps = f16_ulps(u[f][filled], ref.u[filled])
-        assert ulps.max() <= 1.0
-        assert st["frame_K"][f] == ref.K and st["frame_filled"][f] == ref.n_filled
+    import paper_1611_05319_amd as gf
+    from paper_1611_05319_amd import autotune
+
+    if name == "autotuned":  # the launch shape bench.py measures
+        dev = torch.device("cuda:0")
+        i4, l4, g4 = (torch.from_numpy(a).to(dev) for a in (w.image, w.label, w.guide))
+        p = autotune.tune(i4, l4, g4, gf.Params(eps=w.eps, mu=w.mu), reps=3)
+        del i4, l4, g4
+        return {k: getattr(p, k) for k in ("engine", "group", "blocks_per_cu", "tile_w", "tile_h",
+                                           "pass_shells", "tile_threads")}
+    return dict(LAUNCH[name])
+
+
+@pytest.mark.parametrize("launch", ["tiled", "front", "autotuned"])
+def test_config4_batched_all_frames(config4_reference, launch):
+    """Every frame of the 64-frame binary16 batch, at full size, on both
+    engines and on the launch shape the autotuner picks: shell maps bit-exact,
+    colours within one binary16 spacing."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    w, refs = config4_reference
+    kw = _config4_launch(launch, w)
+    banner(f"c4 fill launch={launch} {kw}")
+    dev = torch.device("cuda:0")
+    i4, l4, g4 = (torch.from_numpy(a).to(dev) for a in (w.image, w.label, w.guide))
+    r = gf.fill_batched(i4, l4, g4, gf.Params(eps=w.eps, mu=w.mu, **kw))
+    torch.cuda.synchronize()
+    st = r.host_stats()
+    assert not st["sync_timeout"]
+    differing = 0
+    for f, (rs, ru, rK, rn) in enumerate(refs):
+        s = r.shell[f].cpu().numpy()
+        np.testing.assert_array_equal(s, rs, err_msg=f"frame {f}")
+        filled = rs >= 0
+        u = r.out[f].cpu().numpy()
+        # unfilled pixels keep their input exactly
+        np.testing.assert_array_equal(u[~filled], w.image[f][~filled])
+        ulps = f16_ulps(u[filled].astype(np.float64), ru[filled].astype(np.float64))
+        assert ulps.max() <= 1.0, f"frame {f}: {ulps.max()} binary16 spacings"
+        differing += int((ulps > 0).sum())
+        assert st["frame_K"][f] == rK and st["frame_filled"][f] == rn, f"frame {f}"
+    total = sum(rn for _, _, _, rn in refs)
+    banner(f"c4 launch={launch}: {differing} of {3 * total} filled values differ by one binary16 spacing")
+    assert differing <= 1e-3 * 3 * total
+    assert st["K"] == max(rK for _, _, rK, _ in refs) and st["filled"] == total
 
 
 @pytest.mark.parametrize("engine", ENGINES)
