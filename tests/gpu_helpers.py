@@ -70,3 +70,47 @@ def f16_ulps(a, b):
     b16 = b.astype(np.float16)
     sp = np.spacing(np.abs(b16)).astype(np.float64)
     return np.abs(a - b) / sp
+
+
+def f16_one_step(img_in, label, guide, u_gpu, s_gpu, eps=3.0, mu=50.0, c=-1.0, ghost=True):
+    """Every binary16 value the GPU filled, against the FP64 oracle evaluated
+    from the GPU's own state at that value's shell (the pixels filled before
+    shell k carry the GPU's colours): the GPU value must be that FP64 value
+    rounded to binary16 (nearest, ties to even) unless the FP64 value lies on
+    a rounding tie (halfway between two binary16 numbers, to FP64 precision),
+    where either neighbour is correctly rounded from the exact value.  A value
+    that differs from the oracle's chained fill because an earlier value
+    differed is thereby checked against its own inputs.
+    Returns (values checked, values at ties that rounded the other way,
+    values that are not the correctly rounded FP64 value)."""
+    import oracle
+
+    H, W = label.shape
+    u_gpu = u_gpu.astype(np.float64)
+    base = img_in.astype(np.float64)
+    n_vals = n_ties = n_bad = 0
+    K = int(s_gpu.max()) + 1
+    for k in range(K):
+        at = s_gpu == k
+        if not at.any():
+            continue
+        done = (s_gpu >= 0) & (s_gpu < k)
+        lab = label.copy()
+        lab[done] = 0
+        state = base.copy()
+        state[done] = u_gpu[done]
+        r = oracle.fill(state, lab, guide, eps=eps, mu=mu, c=c, ghost=ghost, max_shells=1)
+        assert (r.shell[at] == 0).all(), f"shell {k}: the one-step oracle fills another set"
+        v = r.u[at]                       # FP64, before any rounding
+        g = u_gpu[at]
+        rn = v.astype(np.float16).astype(np.float64)
+        off = g != rn
+        if off.any():
+            lo = np.minimum(g, rn)
+            hi = np.maximum(g, rn)
+            adjacent = np.nextafter(lo.astype(np.float16), np.float16(np.inf)).astype(np.float64) == hi
+            tie = off & adjacent & (np.abs(v - (lo + hi) / 2) <= 1e-12 * np.abs(v))
+            n_ties += int(tie.sum())
+            n_bad += int((off & ~tie).sum())
+        n_vals += int(v.size)
+    return n_vals, n_ties, n_bad
