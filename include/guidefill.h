@@ -140,6 +140,28 @@ gf_status gf_fill_batched(const void *img_in, void *img_out, int B, int H, int W
                           int32_t *order_out, int32_t *shell_offsets, int32_t *front_hist,
                           int kcap, void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * gf_fill_batched for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc.  Same
+ * arguments, results and errors as gf_fill_batched, without the workspace:
+ * the call uses the library's own scratch, a 16 MiB (GF_SCRATCH_BYTES) array
+ * that each device holds from the time it loads the library until the
+ * process ends, and calls no allocating routine.  A request whose workspace
+ * (gf_workspace_size) exceeds the scratch returns GF_EINVAL with the sizes in
+ * gf_last_error: at most about one 1920 x 1080 frame with GF_ENGINE_FRONT,
+ * about 200 000 tiles (90 such frames at the default tile) with
+ * GF_ENGINE_TILED.  Every call on a device shares that device's scratch and
+ * leaves its contents behind (each launch re-initialises what it reads):
+ * calls that overlap in time on one device race, whatever their streams, and
+ * must be serialised by the caller.
+ */
+#define GF_SCRATCH_BYTES ((size_t)16 << 20)
+gf_status gf_fill_batched_noalloc(const void *img_in, void *img_out, int B, int H, int W, int C,
+                                  gf_dtype dt, const uint8_t *label, const float *guide,
+                                  const gf_params *p, int32_t *shell_out, int32_t *stats,
+                                  int32_t *order_out, int32_t *shell_offsets, int32_t *front_hist,
+                                  int kcap, void *stream);
+
 /* One frame: gf_fill_batched with B = 1. */
 gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,
                   const uint8_t *label, const float *guide, const gf_params *p,

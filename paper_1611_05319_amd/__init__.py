@@ -23,8 +23,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_backward",
-    "GuidefillFn",
+    "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_batched_noalloc",
+    "fill_backward", "GuidefillFn",
     "library_path", "load", "stats_fields", "tile_geometry", "ENGINE_TILED", "ENGINE_FRONT",
 ]
 
@@ -34,6 +34,7 @@ _lib = None
 _lock = threading.Lock()
 
 GF_F32, GF_F16 = 0, 1
+SCRATCH_BYTES = 16 << 20  # GF_SCRATCH_BYTES: the static workspace of gf_fill_batched_noalloc
 _STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "unsupported request"}
 (STAT_SHELLS, STAT_FILLED, STAT_HOLE, STAT_MAX_FRONT, STAT_LABEL_ERR, STAT_ORDER_TRUNC,
  STAT_SYNC_TIMEOUT, STAT_WORKGROUPS) = range(8)
@@ -101,6 +102,8 @@ def load():
         lib.gf_backward_workspace_size.restype = Z
         lib.gf_fill_batched.argtypes = [P, P, I, I, I, I, I, P, P, PP, P, P, P, P, P, I, P, Z, P]
         lib.gf_fill_batched.restype = I
+        lib.gf_fill_batched_noalloc.argtypes = [P, P, I, I, I, I, I, P, P, PP, P, P, P, P, P, I, P]
+        lib.gf_fill_batched_noalloc.restype = I
         lib.gf_fill.argtypes = [P, P, I, I, I, I, P, P, PP, P, P, P, Z, P]
         lib.gf_fill.restype = I
         lib.gf_fill_backward.argtypes = [P, P, I, I, I, I, I, P, P, P, I, PP, P, P, P, Z, P]
@@ -264,6 +267,30 @@ def fill_batched(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
                              _ptr(hist), int(kcap), _ptr(ws), ws.numel(), _stream_ptr(dev))
     _check(rc, "gf_fill_batched")
     return FillResult(out, shell, stats, order, offs, hist)
+
+
+def fill_batched_noalloc(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,
+                         params: Params, out: torch.Tensor, shell: torch.Tensor,
+                         stats: torch.Tensor, stream: torch.cuda.Stream | None = None) -> FillResult:
+    """gf_fill_batched_noalloc: fill_batched into caller-provided `out`, `shell`
+    and `stats` (int32, 8 + 4 B entries) with the library's static scratch as
+    the workspace; neither this function nor the library allocates."""
+    dev = _require_device(img, label, guide, out, shell, stats)
+    B, H, W, C = img.shape
+    if tuple(label.shape) != (B, H, W) or tuple(guide.shape) != (B, H, W, 2):
+        raise ValueError("shape mismatch between img, label and guide")
+    if tuple(out.shape) != tuple(img.shape) or tuple(shell.shape) != (B, H, W):
+        raise ValueError("shape mismatch of out or shell")
+    if stats.dtype != torch.int32 or stats.numel() < STAT_FRAME0 + STAT_PER_FRAME * B:
+        raise ValueError("stats must be int32 with 8 + 4 B entries")
+    lib = load()
+    cp = params.c_struct()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = lib.gf_fill_batched_noalloc(_ptr(img), _ptr(out), B, H, W, C, _dtype_code(img), _ptr(label),
+                                     _ptr(guide), ctypes.byref(cp), _ptr(shell), _ptr(stats), None,
+                                     None, None, 0, ctypes.c_void_p(s.cuda_stream))
+    _check(rc, "gf_fill_batched_noalloc")
+    return FillResult(out, shell, stats)
 
 
 def fill(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,

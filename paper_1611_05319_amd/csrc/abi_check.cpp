@@ -115,6 +115,14 @@ int main() {
     CHECK(gf_fill(fake, fake, 8, 8, 3, GF_F32, (const uint8_t *)fake, (const float *)fake, &p,
                   (int32_t *)fake, (int32_t *)fake, fake, 16, nullptr) == GF_EINVAL);
 
+    // the no-allocation entry point: requests beyond its scratch
+    p = defaults();
+    p.engine = GF_ENGINE_FRONT;
+    CHECK(gf_fill_batched_noalloc(fake, fake, 2, 1080, 1920, 3, GF_F32, (const uint8_t *)fake,
+                                  (const float *)fake, &p, (int32_t *)fake, (int32_t *)fake, nullptr,
+                                  nullptr, nullptr, 0, nullptr) == GF_EINVAL);
+    CHECK(strstr(gf_last_error(), "scratch") != nullptr);
+
     // the adjoint
     p = defaults();
     const size_t nb = gf_backward_workspace_size(1, 8, 8, 3, GF_F32, &p);

@@ -382,6 +382,38 @@ bool layout_for(int B, int H, int W, int C, int dt, const gf_params *p, WsLayout
     return true;
 }
 
+// Library-owned scratch for gf_fill_batched_noalloc: a workspace that lives
+// in the code object, so callers that cannot allocate device memory (code
+// under graph capture, serving loops) still get one.  Each device that loads
+// the library holds its own zero-initialised copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, never a device address: the
+// device address is looked up once per device (scratch_on_device) and only
+// that pointer is handed to kernels.
+constexpr size_t kScratchBytes = GF_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of this device's scratch; the first call on a device looks
+// it up (with that device current) and keeps it.  nullptr on failure (the
+// HIP error is recorded for gf_last_error).
+void *scratch_on_device(int dev) {
+    static std::mutex mu;
+    static void *ptrs[64] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64) {
+        snprintf(g_last_error, sizeof g_last_error, "device index %d outside 0..63", dev);
+        return nullptr;
+    }
+    if (ptrs[dev]) return ptrs[dev];
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        set_err("hipGetSymbolAddress(scratch)", e);
+        return nullptr;
+    }
+    ptrs[dev] = ptr;
+    return ptr;
+}
+
 size_t workspace_bytes(int B, int H, int W, int C, int dt, const gf_params *p) {
     if (!p || B < 1 || H < 1 || W < 1 || C < 1 || (dt != GF_F32 && dt != GF_F16)) return 0;
     WsLayout L;
@@ -553,6 +585,31 @@ gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, i
 }  // namespace
 
 extern "C" {
+
+gf_status gf_fill_batched_noalloc(const void *img_in, void *img_out, int B, int H, int W, int C,
+                                  gf_dtype dt_arg, const uint8_t *label, const float *guide,
+                                  const gf_params *p, int32_t *shell_out, int32_t *stats,
+                                  int32_t *order_out, int32_t *shell_offsets, int32_t *front_hist,
+                                  int kcap, void *stream) {
+    const int dt = raw_enum(&dt_arg);
+    gf_status st = validate(p, B, H, W, C, dt);
+    if (st != GF_OK) return st;
+    const size_t need = workspace_bytes(B, H, W, C, dt, p);
+    if (need == 0) return GF_EINVAL;
+    if (need > kScratchBytes) {
+        snprintf(g_last_error, sizeof g_last_error,
+                 "the request needs %zu bytes of workspace; the library's scratch holds %zu",
+                 need, kScratchBytes);
+        return GF_EINVAL;
+    }
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_err("hipGetDevice", e); return GF_EDEVICE; }
+    void *ws = scratch_on_device(dev);
+    if (!ws) return GF_EDEVICE;
+    return fill_batched(img_in, img_out, B, H, W, C, dt, label, guide, p, shell_out, stats,
+                        order_out, shell_offsets, front_hist, kcap, ws, kScratchBytes, stream);
+}
 
 gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dtype dt,
                   const uint8_t *label, const float *guide, const gf_params *p,

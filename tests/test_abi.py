@@ -187,3 +187,20 @@ def test_python_binding_fails_loudly_without_device():
     with pytest.raises(ValueError):
         gf.fill(img, lab, g)
 
+
+def test_noalloc_rejects_requests_beyond_the_scratch(lib):
+    """The no-allocation entry point checks the workspace it would need against
+    its static scratch before any HIP call."""
+    import paper_1611_05319_amd as gf
+
+    p = gf.Params(engine=gf.ENGINE_FRONT).c_struct()
+    fake = ctypes.c_void_p(1 << 20)
+    # two 1920 x 1080 frames need two front lists of 2 x 8.3 MB: beyond 16 MiB
+    assert lib.gf_workspace_size(2, 1080, 1920, 3, 0, ctypes.byref(p)) > gf.SCRATCH_BYTES
+    rc = lib.gf_fill_batched_noalloc(fake, fake, 2, 1080, 1920, 3, 0, fake, fake, ctypes.byref(p),
+                                     fake, fake, None, None, None, 0, None)
+    assert rc == -1
+    assert b"scratch" in lib.gf_last_error()
+    bad = gf.Params(eps=0.5).c_struct()
+    assert lib.gf_fill_batched_noalloc(fake, fake, 1, 8, 8, 3, 0, fake, fake, ctypes.byref(bad),
+                                       fake, fake, None, None, None, 0, None) == -1
