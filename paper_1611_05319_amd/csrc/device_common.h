@@ -24,7 +24,7 @@ template <int G> __host__ __device__ constexpr int per_lane() {
     return G <= 4 ? 8 : (G == 16 ? 5 : kPerLaneMax);
 }
 __host__ __device__ inline int per_lane_of(int G) { return G <= 4 ? 8 : (G == 16 ? 5 : kPerLaneMax); }
-constexpr int kStageCap = 2048;   // LDS staging entries per workgroup
+constexpr int kStageCap = 1024;   // LDS staging entries per workgroup
 constexpr int kFrameCap = 64;     // frames with LDS statistics accumulators (global engine)
 constexpr int kXcd = 8;           // XCDs of the MI355X; workgroups are dealt round robin
 constexpr int kCtlWords = 1024;   // control block (int32) at the start of the workspace
@@ -287,7 +287,7 @@ struct LaunchSync {
 // before touching any of them.  Returns false in a workgroup that does not
 // take part: it must return at once.  Logical indices are consecutive within
 // an XCD group, so contiguous ranges of pixels or tiles stay in one L2.
-__device__ bool launch_start(int32_t *ctl, const LaunchSync &ls, GridInfo &gi, int32_t *z1, int n1,
+__device__ __attribute__((always_inline)) bool launch_start(int32_t *ctl, const LaunchSync &ls, GridInfo &gi, int32_t *z1, int n1,
                              int32_t *z2, int n2, int32_t *z3, int n3) {
     __shared__ int s_role;  // 1 leader, 0 taking part, -1 not taking part
     __shared__ int s_ticket;
@@ -393,7 +393,7 @@ __device__ bool launch_start(int32_t *ctl, const LaunchSync &ls, GridInfo &gi, i
 // relaxed spin (an acquire load would invalidate the caches on every
 // iteration) followed by one acquire.
 
-__device__ void grid_sync(int32_t *ctl, const GridInfo &gi) {
+__device__ __attribute__((always_inline)) void grid_sync(int32_t *ctl, const GridInfo &gi) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -444,7 +444,7 @@ struct SyncSum {
     unsigned flags;
 };
 
-__device__ SyncSum grid_sync_sum(int32_t *ctl, const GridInfo &gi, unsigned a, bool flag) {
+__device__ __attribute__((always_inline)) SyncSum grid_sync_sum(int32_t *ctl, const GridInfo &gi, unsigned a, bool flag) {
     __shared__ unsigned long long s_word;
     typedef unsigned long long u64;
     constexpr u64 kLow48 = (1ull << 48) - 1ull;
@@ -518,7 +518,7 @@ __device__ inline int max_x(const int32_t *ctl, int field) {
 
 // ball offsets {(n, m): 0 < n^2 + m^2 <= eps^2}, m ascending then n, and the
 // reciprocal distances 1/|(n, m)| (the rotation preserves them)
-__device__ void build_offsets(double eps, short2 *off, double *rinv, int *T) {
+__device__ __attribute__((always_inline)) void build_offsets(double eps, short2 *off, double *rinv, int *T) {
     if (threadIdx.x == 0) {
         int R = (int)floor(eps);
         int cnt = 0;

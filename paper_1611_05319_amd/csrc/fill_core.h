@@ -2,8 +2,9 @@
 // 1611.05319): Algorithm 1's weighted average over the readable points of the
 // rotated ball of ghost pixels (Sec. 3.1, 3.3, eqn:weight, eqn:bilinearDef),
 // with onion order or the smart-order test (Sec. 3.4, eqn:confidence,
-// eqn:ready).  The state and colours are read through a view: the frame in
-// global memory, or a tile window staged in LDS.
+// eqn:ready).  The state and colours are read from a window staged in LDS: a
+// tile window (tiled engine) or one pixel's neighbourhood (global-front
+// engine, adjoint).
 //
 // Precision: every quantity that decides a shell (the ghost offsets, their
 // floors and lattice-line tests, the smart-order confidence) is FP64 with no
@@ -22,24 +23,6 @@ namespace gfk {
 // colours as FP32
 __device__ inline float px_f32(float v) { return v; }
 __device__ inline float px_f32(__half v) { return __half2float(v); }
-
-// frame in global memory (state = shell map; colours C per pixel, unpadded)
-template <typename TS> struct GlobalView {
-    const int32_t *S;
-    const TS *U;
-    int W, H, C;
-    __device__ bool inside(int x0, int y0, int x1, int y1) const {
-        return x0 >= 0 && y0 >= 0 && x1 < W && y1 < H;
-    }
-    __device__ int index(int x, int y) const { return y * W + x; }
-    __device__ int pitch() const { return W; }
-    __device__ int32_t state_at(int i) const { return S[i]; }
-    __device__ void colours(int i, float o[4]) const {
-        const TS *p = U + (long long)i * C;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) o[ch] = ch < C ? px_f32(p[ch]) : 0.0f;
-    }
-};
 
 // channels of a pixel in an LDS window: always 4 (padding never read into a
 // result), so a pixel's colours are one vector load
@@ -90,7 +73,7 @@ template <typename TS> struct LdsView {
 // R = floor(eps) < G; off / rinv: the padded offset table (per_lane<G>() * G
 // entries).
 template <typename TS, int G, typename V>
-__device__ bool fill_core(const V &v, int X, int Y, double gx, double gy, bool ghost,
+__device__ __attribute__((always_inline)) bool fill_core(const V &v, int X, int Y, double gx, double gy, bool ghost,
                           const short2 *off, const double *rinv, int T, int R, int k, int l,
                           double a, double c, double out[4]) {
     const bool rot = ghost && (gx != 0.0 || gy != 0.0);

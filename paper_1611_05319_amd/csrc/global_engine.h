@@ -92,16 +92,77 @@ __device__ inline void copy_range(const char *src, char *dst, size_t b0, size_t 
     for (size_t j = (v1 > b0 ? v1 : b0) + tid; j < b1; j += nt) dst[j] = src[j];
 }
 
+// Per-group neighbourhood window in LDS: the (2D + 1)^2 pixels around a front
+// pixel, D = ceil(eps) (every bilinear support of its ball lies within D
+// pixels in each direction), with their states and colours (4 slots per
+// pixel).  The group's lanes stage it with loads along the window rows, so
+// the fill's many support reads become LDS reads instead of scattered global
+// gathers.  Pixels outside the frame are staged as bystanders (never
+// readable), as an out-of-frame support is unreadable.
+template <typename TS> __host__ __device__ inline int window_bytes(int D) {
+    const int WN = (2 * D + 1) * (2 * D + 1);
+    return ((WN * 4 + 15) & ~15) + ((WN * 4 * (int)sizeof(TS) + 15) & ~15);
+}
+
+template <typename TS>
+__device__ inline void store_colours(TS *dst, const float c[4]);
+template <> __device__ inline void store_colours<float>(float *dst, const float c[4]) {
+    *reinterpret_cast<float4 *>(__builtin_assume_aligned(dst, 16)) = make_float4(c[0], c[1], c[2], c[3]);
+}
+template <> __device__ inline void store_colours<__half>(__half *dst, const float c[4]) {
+    uint2 v;
+    v.x = (unsigned)__half_as_ushort(__float2half_rn(c[0])) | ((unsigned)__half_as_ushort(__float2half_rn(c[1])) << 16);
+    v.y = (unsigned)__half_as_ushort(__float2half_rn(c[2])) | ((unsigned)__half_as_ushort(__float2half_rn(c[3])) << 16);
+    *reinterpret_cast<uint2 *>(__builtin_assume_aligned(dst, 8)) = v;
+}
+
+// Stage the window of pixel (X, Y) of frame f; lane l of the group takes the
+// window pixels l, l + G, ...  The states are the shell map as it stands:
+// another group's concurrent writes in this shell (s = k for a pixel it fills,
+// the next-front mark) are unreadable at shell k whenever they are seen, so
+// the readable sets do not depend on the timing.
 template <typename TS, int G>
-__device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const double *rinv, int T,
-                                  long long gidx, float2 gv, int k, int l) {
-    const long long f = gidx / A.HW;
-    const int p = (int)(gidx - f * A.HW);
-    const int Y = p / A.W, X = p - Y * A.W;
-    GlobalView<TS> v{A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
-                     A.W, A.H, A.C};
+__device__ inline void stage_window(const int32_t *S, const TS *U, int W, int H, int C, int X, int Y,
+                                    int D, int32_t *st, TS *col, int l) {
+    const int WW = 2 * D + 1, WN = WW * WW;
+    int wy = 0, wx = l;
+    while (wx >= WW) { wx -= WW; ++wy; }
+    // window pixel (wx, wy): state and colours (channels past C repeat channel
+    // C - 1, never used, so no load is conditional on C)
+    auto fetch = [&](int wxx, int wyy, int32_t &s, float c[4]) {
+        const int x = X - D + wxx, y = Y - D + wyy;
+        s = S_BYSTANDER;
+        c[0] = c[1] = c[2] = c[3] = 0.0f;
+        if (x >= 0 && x < W && y >= 0 && y < H) {
+            const long long q = (long long)y * W + x;
+            s = S[q];
+            const TS *p = U + q * C;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) c[ch] = px_f32(p[min(ch, C - 1)]);
+        }
+    };
+    for (int i = l; i < WN; i += G) {
+        int32_t sv;
+        float cv[4];
+        fetch(wx, wy, sv, cv);
+        st[i] = sv;
+        store_colours<TS>(col + i * 4, cv);
+        wx += G;
+        while (wx >= WW) { wx -= WW; ++wy; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the group's lanes read each other's stores
+}
+
+// Fill front pixel gidx at shell k from its staged window; lane 0 stores the
+// colour and the shell.  Returns ready.
+template <typename TS, int G>
+__device__ __attribute__((always_inline)) bool global_fill_pixel(const FillArgs &A, const short2 *off, const double *rinv, int T,
+                                  long long gidx, float2 gv, int k, int l, int D, const int32_t *st,
+                                  const TS *col) {
+    const int WW = 2 * D + 1;
+    LdsView<TS> v{st, col, WW, WW, A.C, 4};
     double val[4];
-    if (!fill_core<TS, G>(v, X, Y, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T,
+    if (!fill_core<TS, G>(v, D, D, (double)gv.x, (double)gv.y, A.ghost != 0, off, rinv, T,
                           (int)floor(A.eps), k, l, A.a, A.c, val))
         return false;
     if (l == 0) {
@@ -117,6 +178,7 @@ __device__ bool global_fill_pixel(const FillArgs &A, const short2 *off, const do
 // two for 16-lane groups, whose 5 offsets per lane need more registers
 template <typename TS, int G>
 __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];  // one neighbourhood window per group
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
     __shared__ int s_T;
@@ -296,6 +358,10 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
     const int nG = kBlock / G;
     const int gi = tid / G;       // group within the workgroup
     const int l = tid & (G - 1);  // lane within the group
+    const int D = (int)ceil(A.eps);
+    const int WW = 2 * D + 1, WN = WW * WW;
+    int32_t *w_st = reinterpret_cast<int32_t *>(smem + gi * window_bytes<TS>(D));
+    TS *w_col = reinterpret_cast<TS *>(reinterpret_cast<unsigned char *>(w_st) + ((WN * 4 + 15) & ~15));
     Stage lst{s_list, &s_list_n, kStageCap};
     Stage ord{s_ord, &s_ord_n, kStageCap};
     const bool want_order = A.order != nullptr;
@@ -342,18 +408,23 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                     GF_TCNT(8, 1);
                     if (item < cn) {
                         const long long gidx = s_item[item];
-                        const bool ok =
-                            global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l);
                         const long long f = gidx / A.HW;
                         const int p = (int)(gidx - f * A.HW);
+                        const int y = p / W, x = p - y * W;
+                        stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
+                                            W, H, A.C, x, y, D, w_st, w_col, l);
+                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item],
+                                                                 k, l, D, w_st, w_col);
                         if (ok) {
                             if (l < 8) {  // emit the unfilled 8-neighbours (dedup by CAS on the map)
                                 const int d = l < 4 ? l : l + 1;
-                                const int y = p / W, x = p - y * W;
-                                const int xx = x + d % 3 - 1, yy = y + d / 3 - 1;
-                                if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                                const int dxn = d % 3 - 1, dyn = d / 3 - 1;
+                                const int xx = x + dxn, yy = y + dyn;
+                                // the window's state filters: a state only leaves S_HOLE in a shell
+                                if (xx >= 0 && xx < W && yy >= 0 && yy < H &&
+                                    w_st[(D + dyn) * WW + D + dxn] == S_HOLE) {
                                     int32_t *sp = A.shell + f * A.HW + (long long)yy * W + xx;
-                                    if (*sp == S_HOLE && atomicCAS(sp, S_HOLE, S_FRONT) == S_HOLE)
+                                    if (atomicCAS(sp, S_HOLE, S_FRONT) == S_HOLE)
                                         stage_push(lst, (int)(f * A.HW + (long long)yy * W + xx),
                                                    nxt_list, nxt_cnt);
                                 }
@@ -400,7 +471,13 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                     if (mybit >= 0) {
                         const long long px = base + wave_base + mybit;
                         const float2 gv = reinterpret_cast<const float2 *>(A.guide)[px];
-                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, gv, k, l);
+                        const long long f = px / A.HW;
+                        const int q = (int)(px - f * A.HW);
+                        const int y = q / W, x = q - y * W;
+                        stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
+                                            W, H, A.C, x, y, D, w_st, w_col, l);
+                        const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, gv, k, l, D,
+                                                                 w_st, w_col);
                         if (ok && l == 0) on_filled(px);
                     }
                 }
@@ -530,20 +607,22 @@ __device__ inline int block_exclusive_scan(int v, int *s_wave, int *total) {
 // ubar(x) w_j / S times the bilinear basis values into the support pixels.
 // agg: this group's LDS patch of (2D + 1)^2 pixels x C floats, or nullptr.
 template <typename TS, int G>
-__device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rinv, int T,
-                          long long gidx, float2 gv, int k, int l, float *agg, int D) {
+__device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const short2 *off,
+                                                         const double *rinv, int T, long long gidx,
+                                                         float2 gv, int k, int l, float *agg, int D,
+                                                         const int32_t *wst, const TS *wcol) {
     const long long f = gidx / A.HW;
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
     const int W = A.W;
     const int C = A.C;
+    const int WW = 2 * D + 1;  // the staged window: x at (D, D)
     float *GI = A.grad_img;
     // the adjoint arriving at x is complete: every shell after k is done
     double ub[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
         if (ch < C) ub[ch] = (double)GI[gidx * C + ch];
-    const int32_t *S = A.shell + f * A.HW;
     const double gx = (double)gv.x, gy = (double)gv.y;
     const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
     double cs = 0.0, sn = 0.0, L = 1.0;
@@ -552,8 +631,9 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
         cs = gx / L;
         sn = gy / L;
     }
-    const TS *U = reinterpret_cast<const TS *>(A.img) + f * A.HW * C;
-    // pass 1: geometry and readable set (kept for the other passes)
+    // pass 1: geometry and readable set (kept for the other passes); supports
+    // as window indices (every support lies inside the window; pixels outside
+    // the frame are staged as bystanders, hence unreadable)
     double fxs[kPerLaneMax], fys[kPerLaneMax], q[kPerLaneMax];
     int base[kPerLaneMax];
     unsigned rmask = 0, exmask = 0, eymask = 0;
@@ -570,20 +650,15 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
             rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
             const double fx0 = floor(ox), fy0 = floor(oy);
             const bool ex = (ox == fx0), ey = (oy == fy0);
-            const int x0 = X + (int)fx0, y0 = Y + (int)fy0;
-            const int x1 = x0 + (ex ? 0 : 1), y1 = y0 + (ey ? 0 : 1);
             fxs[r] = ex ? 0.0 : ox - fx0;
             fys[r] = ey ? 0.0 : oy - fy0;
             exmask |= ex ? (1u << r) : 0u;
             eymask |= ey ? (1u << r) : 0u;
-            bool rd = false;
-            if (x0 >= 0 && y0 >= 0 && x1 < A.W && y1 < A.H) {
-                base[r] = y0 * W + x0;
-                const int32_t a0 = S[y0 * W + x0], a1 = S[y0 * W + x1];
-                const int32_t a2 = S[y1 * W + x0], a3 = S[y1 * W + x1];
-                rd = ((int)readable(a0, k) & (int)readable(a1, k) & (int)readable(a2, k) &
-                      (int)readable(a3, k)) != 0;
-            }
+            const int b = (D + (int)fy0) * WW + (D + (int)fx0);
+            base[r] = b;
+            const int dx = ex ? 0 : 1, dy = ey ? 0 : WW;
+            const bool rd = ((int)readable(wst[b], k) & (int)readable(wst[b + dx], k) &
+                             (int)readable(wst[b + dy], k) & (int)readable(wst[b + dy + dx], k)) != 0;
             const double tp = (-gy) * ox + gx * oy;
             q[r] = A.a * tp * tp;
             if (rd) {
@@ -623,15 +698,17 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
             By += wr * dly;
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
             const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
-            const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W),
+            const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : WW),
                       i11 = i01 + (ex ? 0 : 1);
+            float c00[4], c10[4], c01[4], c11[4];
+            lds_colours<TS>(wcol + i00 * 4, c00);
+            lds_colours<TS>(wcol + i10 * 4, c10);
+            lds_colours<TS>(wcol + i01 * 4, c01);
+            lds_colours<TS>(wcol + i11 * 4, c11);
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
-                    const double u00 = load_px(U + (long long)i00 * C + ch);
-                    const double u10 = load_px(U + (long long)i10 * C + ch);
-                    const double u01 = load_px(U + (long long)i01 * C + ch);
-                    const double u11 = load_px(U + (long long)i11 * C + ch);
+                    const double u00 = c00[ch], u10 = c10[ch], u01 = c01[ch], u11 = c11[ch];
                     const double v = wx0 * wy0 * u00 + wx1 * wy0 * u10 + wx0 * wy1 * u01 +
                                      wx1 * wy1 * u11;
                     const double vpx = ex ? 0.0 : wy0 * (u10 - u00) + wy1 * (u11 - u01);
@@ -660,13 +737,12 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     }
     // pass 3: pass the adjoint to the bilinear supports.  With a small ball the
     // contributions are first summed per support pixel in the group's LDS
-    // patch of (2D + 1)^2 pixels around x (D = ceil(eps) bounds every support
-    // offset), so each touched pixel takes one global atomic per channel
-    // instead of one per ghost point that reads it.
+    // patch of (2D + 1)^2 pixels around x (laid out as the window), so each
+    // touched pixel takes one global atomic per channel instead of one per
+    // ghost point that reads it.
     const long long fo = f * A.HW;
     if (agg) {
-        const int P2 = 2 * D + 1;
-        for (int i = l; i < P2 * P2 * C; i += G) agg[i] = 0.0f;
+        for (int i = l; i < WW * WW * C; i += G) agg[i] = 0.0f;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
         for (int r = 0; r < kPerLaneMax; ++r) {
@@ -674,9 +750,8 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
                 const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
                 const double lam = w[r] * inv;
                 const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
-                const int by = base[r] / W, bx = base[r] - by * W;
-                const int j00 = ((by - Y + D) * P2 + (bx - X + D)) * C;
-                const int j10 = j00 + (ex ? 0 : C), j01 = j00 + (ey ? 0 : P2 * C),
+                const int j00 = base[r] * C;
+                const int j10 = j00 + (ex ? 0 : C), j01 = j00 + (ey ? 0 : WW * C),
                           j11 = j01 + (ex ? 0 : C);
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch) {
@@ -691,8 +766,8 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int i = l; i < P2 * P2; i += G) {
-            const int yy = Y - D + i / P2, xx = X - D + i % P2;
+        for (int i = l; i < WW * WW; i += G) {
+            const int yy = Y - D + i / WW, xx = X - D + i % WW;
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
@@ -709,8 +784,9 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
             const double lam = w[r] * inv;
             const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
-            const long long i00 = fo + base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W),
-                            i11 = i01 + (ex ? 0 : 1);
+            const int by = base[r] / WW, bx = base[r] - by * WW;
+            const long long i00 = fo + (long long)(Y - D + by) * W + (X - D + bx),
+                            i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W), i11 = i01 + (ex ? 0 : 1);
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
@@ -730,12 +806,19 @@ __device__ void bwd_pixel(const BwdArgs &A, const short2 *off, const double *rin
     }
 }
 
+// Bytes of dynamic LDS per group of the adjoint's reverse shells: the
+// neighbourhood window, then the support patch
+template <typename TS> __host__ __device__ inline int bwd_group_bytes(int D, int C) {
+    const int patch = D <= kAggMaxD ? (((2 * D + 1) * (2 * D + 1) * C * 4 + 15) & ~15) : 0;
+    return window_bytes<TS>(D) + patch;
+}
+
 // Bytes of dynamic LDS the adjoint launch takes: the sorting bins, later the
-// groups' support patches
-__host__ __device__ inline size_t bwd_dyn_lds(int G, int D, int C) {
+// groups' windows and support patches
+template <typename TS> __host__ __device__ inline size_t bwd_dyn_lds(int G, int D, int C) {
     const size_t bins = 2 * (size_t)kBwdBins * sizeof(int);
-    const size_t patches = D <= kAggMaxD ? (size_t)(kBlock / G) * (2 * D + 1) * (2 * D + 1) * C * sizeof(float) : 0;
-    return bins > patches ? bins : patches;
+    const size_t groups = (size_t)(kBlock / G) * bwd_group_bytes<TS>(D, C);
+    return bins > groups ? bins : groups;
 }
 
 // One persistent launch: (1) group the filled pixels by shell with a counting
@@ -744,7 +827,7 @@ __host__ __device__ inline size_t bwd_dyn_lds(int G, int D, int C) {
 // through to grad_img and clears grad_guide; (2) replay the shells from the
 // last to the first, one grid barrier apart.
 template <typename TS, int G>
-__global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
+__global__ __launch_bounds__(kBlock, 2) void bwd_kernel(BwdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
@@ -761,6 +844,7 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
     const int C = A.C;
     int *s_bin = reinterpret_cast<int *>(smem);  // per shell: count, then this workgroup's next slot
     int *s_boff = s_bin + kBwdBins;              // per shell: start in order
+    GF_T0();
     // ---- counting sort of the filled pixels by shell -------------------------
     const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
     int K = A.K;
@@ -791,7 +875,9 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
             s_bin[i] = n ? atomicAdd(&gcnt[i], n) : 0;
         }
         if (c == 0 && tid == 0 && s_kend > 0) atomicMax(&A.ctl[G_KEND], s_kend);
+        GF_TACC(0);
         grid_sync(A.ctl, grid);
+        GF_TACC(1);
         if (c == 0 && K < 0) K = ld_ctl(A.ctl, G_KEND);
         const int nb = min(kBwdBins, K - cb);  // shells of this round
         int run = first;
@@ -820,7 +906,9 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
         if (lw == 0)
             for (int i = tid; i < kBwdBins; i += kBlock) A.gcount[((c + 1) & 1) * kBwdBins + i] = 0;
         first = run;
+        GF_TACC(2);
         grid_sync(A.ctl, grid);
+        GF_TACC(3);
         if (cb + kBwdBins >= K) break;
     }
     // ---- reverse shells ---------------------------------------------------------
@@ -829,8 +917,11 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
     const int gi = tid / G, l = tid & (G - 1);
     const int D = (int)ceil(A.eps);
     const bool use_agg = D <= kAggMaxD;
-    const int patch = (2 * D + 1) * (2 * D + 1) * C;
-    float *agg = reinterpret_cast<float *>(smem) + gi * patch;
+    const int WN = (2 * D + 1) * (2 * D + 1);
+    unsigned char *gbase = smem + gi * bwd_group_bytes<TS>(D, C);
+    int32_t *w_st = reinterpret_cast<int32_t *>(gbase);
+    TS *w_col = reinterpret_cast<TS *>(gbase + ((WN * 4 + 15) & ~15));
+    float *agg = reinterpret_cast<float *>(gbase + window_bytes<TS>(D));
     for (int k = K - 1; k >= 0; --k) {
         const long long b0 = ld_ctl(A.offs, k), b1 = ld_ctl(A.offs, k + 1);
         const long long n = b1 - b0;
@@ -846,12 +937,22 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
             __syncthreads();
             for (int base = 0; base < cn; base += nG) {
                 const int item = base + gi;
-                if (item < cn)
-                    bwd_pixel<TS, G>(A, s_off, s_rinv, T, s_item[item], s_gd[item], k, l,
-                                     use_agg ? agg : nullptr, D);
+                if (item < cn) {
+                    const long long gidx = s_item[item];
+                    const long long f = gidx / A.HW;
+                    const int p = (int)(gidx - f * A.HW);
+                    const int y = p / A.W, x = p - y * A.W;
+                    stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.img) + f * A.HW * C,
+                                        A.W, A.H, C, x, y, D, w_st, w_col, l);
+                    bwd_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l,
+                                     use_agg ? agg : nullptr, D, w_st, w_col);
+                }
+                GF_TCNT(6, 1);
             }
         }
+        GF_TACC(4);
         grid_sync(A.ctl, grid);
+        GF_TACC(5);
     }
 }
 

@@ -282,11 +282,13 @@ gf_status launch_persistent(K kernel, const void *args_ptr, int blocks_per_cu, l
 template <typename TS>
 gf_status run_front(const FillArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
-    if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers allow
-    if (G == 8) return launch_persistent(fill_kernel<TS, 8>, &A, bpc, mb, 0, s);
-    if (G == 16) return launch_persistent(fill_kernel<TS, 16>, &A, bpc, mb, 0, s);
-    if (G == 32) return launch_persistent(fill_kernel<TS, 32>, &A, bpc, mb, 0, s);
-    return launch_persistent(fill_kernel<TS, 64>, &A, bpc, mb, 0, s);
+    if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers and LDS allow
+    // one neighbourhood window per group of G lanes
+    const size_t lds = (size_t)(kBlock / G) * window_bytes<TS>((int)ceil(A.eps));
+    if (G == 8) return launch_persistent(fill_kernel<TS, 8>, &A, bpc, mb, lds, s);
+    if (G == 16) return launch_persistent(fill_kernel<TS, 16>, &A, bpc, mb, lds, s);
+    if (G == 32) return launch_persistent(fill_kernel<TS, 32>, &A, bpc, mb, lds, s);
+    return launch_persistent(fill_kernel<TS, 64>, &A, bpc, mb, lds, s);
 }
 
 // threads per tile workgroup
@@ -315,7 +317,7 @@ template <typename TS>
 gf_status run_bwd(const BwdArgs &A, int G, int bpc, hipStream_t s) {
     const long long mb = (A.NP + kBlock - 1) / kBlock;
     if (bpc == 0) bpc = 8;  // as many workgroups per CU as the registers and LDS allow
-    const size_t lds = bwd_dyn_lds(G, (int)ceil(A.eps), A.C);
+    const size_t lds = bwd_dyn_lds<TS>(G, (int)ceil(A.eps), A.C);
     if (G == 8) return launch_persistent(bwd_kernel<TS, 8>, &A, bpc, mb, lds, s);
     if (G == 16) return launch_persistent(bwd_kernel<TS, 16>, &A, bpc, mb, lds, s);
     if (G == 32) return launch_persistent(bwd_kernel<TS, 32>, &A, bpc, mb, lds, s);
@@ -692,5 +694,18 @@ gf_status gf_fill_backward(const float *grad_out, const void *img_out, int B, in
     if (rc == GF_OK) commit_launch(workspace, A.sync);
     return rc;
 }
+
+#ifdef GF_TRACE
+// Profiling builds only: copy the per-workgroup timing accumulators out and
+// clear them.
+int gf_trace_read(long long *host, int n) {
+    if (n > 4096 * kTraceSlots) n = 4096 * kTraceSlots;
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(gf_trace), (size_t)n * sizeof(long long)) != hipSuccess)
+        return -1;
+    static long long zeros[4096 * kTraceSlots];
+    if (hipMemcpyToSymbol(HIP_SYMBOL(gf_trace), zeros, sizeof zeros) != hipSuccess) return -1;
+    return n;
+}
+#endif
 
 }  // extern "C"

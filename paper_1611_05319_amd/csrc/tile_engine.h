@@ -71,7 +71,7 @@ template <typename TS> __host__ __device__ inline size_t tile_lds_bytes(int WN, 
 // from the start from the input, so the copy runs beside the first pass's
 // fills.  Falls back to pixel by pixel where the buffers are not aligned.
 template <typename TS>
-__device__ void copy_known(const TS *__restrict__ in, TS *__restrict__ out, const uint8_t *__restrict__ label,
+__device__ __attribute__((always_inline)) void copy_known(const TS *__restrict__ in, TS *__restrict__ out, const uint8_t *__restrict__ label,
                            int C, long long NP, int share, int shares) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bpp = C * (int)sizeof(TS);                   // 2 .. 16 bytes per pixel
