@@ -85,6 +85,11 @@ typedef struct {
                                pass_shells * ceil(eps) may not exceed tile_w or tile_h */
     int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (auto), 256, 512, 768, 1024;
                                must be 0 with GF_ENGINE_FRONT */
+    double c2;              /* < 0: no data term; >= 0: the data term of eqn:ready2 (Sec. 3.4),
+                               ready also requires |g(x)| > c2, until the first shell in which
+                               that leaves no pixel ready; that shell and the later ones use
+                               eqn:ready (or onion order) alone.  The switch is per frame:
+                               c2 >= 0 needs B == 1 (else GF_EUNSUPPORTED) */
 } gf_params;
 
 /* Layout of the int32 stats array written by gf_fill / gf_fill_batched

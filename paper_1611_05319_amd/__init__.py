@@ -50,12 +50,14 @@ class _Params(ctypes.Structure):
                 ("max_shells", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("pass_shells", ctypes.c_int32), ("tile_threads", ctypes.c_int32)]
+                ("pass_shells", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
+                ("c2", ctypes.c_double)]
 
 
 @dataclass
 class Params:
-    """Fill parameters (gf_params).  c < 0: onion order; c >= 0: smart order.
+    """Fill parameters (gf_params).  c < 0: onion order; c >= 0: smart order;
+    c2 >= 0: the data term of eqn:ready2 (|g| > c2) until it leaves nothing ready.
     engine 0: tiled (LDS windows, pass_shells shells per grid sync);
     engine 1: one grid sync per shell with a global front list."""
 
@@ -72,12 +74,14 @@ class Params:
     tile_h: int = 0
     pass_shells: int = 0
     tile_threads: int = 0
+    c2: float = -1.0
 
     def c_struct(self) -> _Params:
         return _Params(float(self.eps), float(self.mu), float(self.c), int(bool(self.ghost)),
                        int(bool(self.tracking)), int(self.max_shells), int(self.engine),
                        int(self.group), int(self.blocks_per_cu), int(self.tile_w),
-                       int(self.tile_h), int(self.pass_shells), int(self.tile_threads))
+                       int(self.tile_h), int(self.pass_shells), int(self.tile_threads),
+                       float(self.c2))
 
 
 def library_path() -> str:

@@ -32,9 +32,17 @@ struct FillArgs {
     double eps;
     double a;  // mu^2 / (2 eps^2)
     double c;  // < 0 onion
+    double c2; // < 0: no data term; else eqn:ready2's |g| > c2 until it leaves nothing ready
     int ghost;
     LaunchSync sync;  // launch start-up (join words and epoch)
 };
+
+// The data term of eqn:ready2: D(x) = |g(x)| > c2 (FP64, as the shell order
+// depends on it)
+__device__ inline bool data_term_ok(float2 g, double c2) {
+    const double gx = (double)g.x, gy = (double)g.y;
+    return sqrt(gx * gx + gy * gy) > c2;
+}
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
 constexpr int kAggMaxD = 4;    // adjoint: support patches up to (2*4+1)^2 pixels in LDS
@@ -121,7 +129,9 @@ template <> __device__ inline void store_colours<__half>(__half *dst, const floa
 // another group's concurrent writes in this shell (s = k for a pixel it fills,
 // the next-front mark) are unreadable at shell k whenever they are seen, so
 // the readable sets do not depend on the timing.
-template <typename TS, int G>
+// NU > 1: each lane's first NU window pixels are loaded with every load in
+// flight at once (more registers), the rest one after another.
+template <typename TS, int G, int NU = 1>
 __device__ inline void stage_window(const int32_t *S, const TS *U, int W, int H, int C, int X, int Y,
                                     int D, int32_t *st, TS *col, int l) {
     const int WW = 2 * D + 1, WN = WW * WW;
@@ -141,7 +151,27 @@ __device__ inline void stage_window(const int32_t *S, const TS *U, int W, int H,
             for (int ch = 0; ch < 4; ++ch) c[ch] = px_f32(p[min(ch, C - 1)]);
         }
     };
-    for (int i = l; i < WN; i += G) {
+    int i = l;
+    if constexpr (NU > 1) {
+        int32_t sv[NU];
+        float cv[NU][4];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            sv[j] = S_BYSTANDER;
+            if (i + j * G < WN) fetch(wx, wy, sv[j], cv[j]);
+            wx += G;
+            while (wx >= WW) { wx -= WW; ++wy; }
+        }
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            if (i + j * G < WN) {
+                st[i + j * G] = sv[j];
+                store_colours<TS>(col + (i + j * G) * 4, cv[j]);
+            }
+        }
+        i += NU * G;
+    }
+    for (; i < WN; i += G) {
         int32_t sv;
         float cv[4];
         fetch(wx, wy, sv, cv);
@@ -366,15 +396,19 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
     Stage ord{s_ord, &s_ord_n, kStageCap};
     const bool want_order = A.order != nullptr;
     int nk = (int)min((long long)ld_ctl(ctl, G_LIST + 0), A.NP);
-    for (int k = 0; track || total_filled < total_hole; ++k) {
+    // eqn:ready2: the data term holds pixels back until a shell fills nothing;
+    // that shell is then taken again without it (k stays, the iteration it
+    // moves on: the lists and counter rings follow it)
+    bool phase1 = A.c2 >= 0.0;
+    for (int it = 0, k = 0; track || total_filled < total_hole; ++it) {
         if (A.max_shells > 0 && k >= A.max_shells) break;
         if (track && nk == 0) break;
         if (lw == 0 && tid == 0) {
-            ctl[G_LIST + (k + 2) % 3] = 0;
-            ctl[G_ACTIVE + (k + 1) % 3] = 0;
+            ctl[G_LIST + (it + 2) % 3] = 0;
+            ctl[G_ACTIVE + (it + 1) % 3] = 0;
         }
-        int32_t *nxt_list = (k & 1) ? A.listA : A.listB;
-        int32_t *nxt_cnt = &ctl[G_LIST + (k + 1) % 3];
+        int32_t *nxt_list = (it & 1) ? A.listA : A.listB;
+        int32_t *nxt_cnt = &ctl[G_LIST + (it + 1) % 3];
         int my_fill = 0;
         auto on_filled = [&](long long gidx) {
             ++my_fill;
@@ -390,7 +424,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
             }
         };
         if (track) {
-            const int32_t *cur = (k & 1) ? A.listB : A.listA;
+            const int32_t *cur = (it & 1) ? A.listB : A.listA;
             const long long lo = (long long)nk * lw / nblk, hi = (long long)nk * (lw + 1) / nblk;
             // this workgroup's items and their guides are staged in LDS first, so
             // the rounds of groups start from LDS instead of two dependent loads
@@ -406,7 +440,9 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                 for (int base = 0; base < cn; base += nG) {
                     const int item = base + gi;
                     GF_TCNT(8, 1);
-                    if (item < cn) {
+                    if (item < cn && phase1 && !data_term_ok(s_gd[item], A.c2)) {
+                        if (l == 0) stage_push(lst, s_item[item], nxt_list, nxt_cnt);  // waits
+                    } else if (item < cn) {
                         const long long gidx = s_item[item];
                         const long long f = gidx / A.HW;
                         const int p = (int)(gidx - f * A.HW);
@@ -471,6 +507,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                     if (mybit >= 0) {
                         const long long px = base + wave_base + mybit;
                         const float2 gv = reinterpret_cast<const float2 *>(A.guide)[px];
+                        if (phase1 && !data_term_ok(gv, A.c2)) continue;  // waits (group-uniform)
                         const long long f = px / A.HW;
                         const int q = (int)(px - f * A.HW);
                         const int y = q / W, x = q - y * W;
@@ -494,7 +531,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
         __syncthreads();
         if (tid == 0) {
             if (wg_fill) atomicAdd(&ctl[G_FILLED], wg_fill);
-            if (!track && wg_active) atomicAdd(&ctl[G_ACTIVE + k % 3], wg_active);
+            if (!track && wg_active) atomicAdd(&ctl[G_ACTIVE + it % 3], wg_active);
             s_fill_n = 0;
             s_active_n = 0;
         }
@@ -507,7 +544,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
         GF_TACC(3);
         GF_TCNT(7, 1);
         if (lw == 0 && tid == 0) {  // statistics: one workgroup loads what only it needs
-            const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + k % 3);
+            const int front_k = track ? nk : ld_ctl(ctl, G_ACTIVE + it % 3);
             max_front = max(max_front, front_k);
             if (A.front_hist && k < A.kcap) A.front_hist[k] = front_k;
             if (want_order) {
@@ -515,8 +552,14 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                 else trunc = 1;
             }
         }
-        if (ss.flags == 0) break;  // nothing filled: done or stalled
+        if (ss.flags == 0) {  // nothing filled: done or stalled, or the data term's end
+            if (!phase1) break;
+            phase1 = false;
+            if (track) nk = (int)min((long long)ss.a, A.NP);  // every pixel was carried over
+            continue;
+        }
         K = k + 1;
+        ++k;
         if (track) nk = (int)min((long long)ss.a, A.NP);
         else total_filled += ss.a;
         GF_TACC(4);
@@ -610,7 +653,8 @@ template <typename TS, int G>
 __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const short2 *off,
                                                          const double *rinv, int T, long long gidx,
                                                          float2 gv, int k, int l, float *agg, int D,
-                                                         const int32_t *wst, const TS *wcol) {
+                                                         const int32_t *wst, const TS *wcol,
+                                                         const float ubf[4]) {
     const long long f = gidx / A.HW;
     const int p = (int)(gidx - f * A.HW);
     const int Y = p / A.W, X = p - Y * A.W;
@@ -618,11 +662,10 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
     const int C = A.C;
     const int WW = 2 * D + 1;  // the staged window: x at (D, D)
     float *GI = A.grad_img;
-    // the adjoint arriving at x is complete: every shell after k is done
-    double ub[4] = {0.0, 0.0, 0.0, 0.0};
+    // ubar(x), loaded by the caller beside the window
+    double ub[4];
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-        if (ch < C) ub[ch] = (double)GI[gidx * C + ch];
+    for (int ch = 0; ch < 4; ++ch) ub[ch] = (double)ubf[ch];
     const double gx = (double)gv.x, gy = (double)gv.y;
     const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
     double cs = 0.0, sn = 0.0, L = 1.0;
@@ -942,10 +985,15 @@ __global__ __launch_bounds__(kBlock, 2) void bwd_kernel(BwdArgs A) {
                     const long long f = gidx / A.HW;
                     const int p = (int)(gidx - f * A.HW);
                     const int y = p / A.W, x = p - y * A.W;
-                    stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.img) + f * A.HW * C,
-                                        A.W, A.H, C, x, y, D, w_st, w_col, l);
+                    // the adjoint arriving at x is complete (every shell after k
+                    // is done); its load is in flight with the window's
+                    float ubf[4];
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) ubf[ch] = A.grad_img[gidx * C + min(ch, C - 1)];
+                    stage_window<TS, G, 8>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.img) + f * A.HW * C,
+                                           A.W, A.H, C, x, y, D, w_st, w_col, l);
                     bwd_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l,
-                                     use_agg ? agg : nullptr, D, w_st, w_col);
+                                     use_agg ? agg : nullptr, D, w_st, w_col, ubf);
                 }
                 GF_TCNT(6, 1);
             }

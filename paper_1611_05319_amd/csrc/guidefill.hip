@@ -146,7 +146,7 @@ gf_status validate(const gf_params *p, int B, int H, int W, int C, int dt) {
     if (B < 1 || H < 1 || W < 1 || C < 1 || C > 4) return GF_EINVAL;
     if (dt != GF_F32 && dt != GF_F16) return GF_EINVAL;
     if (!(p->eps >= 1.0) || !(p->eps <= 9.0) || !(p->mu > 0.0) || !isfinite(p->mu)) return GF_EINVAL;
-    if (!(p->c == p->c)) return GF_EINVAL;
+    if (!(p->c == p->c) || !(p->c2 == p->c2)) return GF_EINVAL;
     if (p->max_shells < 0) return GF_EINVAL;
     if (p->engine != GF_ENGINE_TILED && p->engine != GF_ENGINE_FRONT) return GF_EINVAL;
     if (p->group != 0 && p->group != 4 && p->group != 8 && p->group != 16 && p->group != 32 &&
@@ -162,6 +162,8 @@ gf_status validate(const gf_params *p, int B, int H, int W, int C, int dt) {
     if (p->tile_threads != 0 && p->engine != GF_ENGINE_TILED) return GF_EINVAL;
     long long np = (long long)B * H * W;
     if (np * C >= (1ll << 31)) return GF_EUNSUPPORTED;  // int32 pixel indices in the lists
+    // the data term's switch is a per-frame event; one launch switches once
+    if (p->c2 >= 0.0 && B > 1) return GF_EUNSUPPORTED;
     return GF_OK;
 }
 
@@ -528,6 +530,7 @@ gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, i
         A.eps = p->eps;
         A.a = a;
         A.c = p->c;
+        A.c2 = p->c2;
         A.ghost = p->ghost ? 1 : 0;
         A.sync = ls;
         const gf_status rc = dt == GF_F32 ? run_front<float>(A, G, p->blocks_per_cu, s)
@@ -576,6 +579,7 @@ gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, i
     A.eps = p->eps;
     A.a = a;
     A.c = p->c;
+    A.c2 = p->c2;
     A.sync = ls;
     const int NT = tile_threads_of(p);
     const gf_status rc = dt == GF_F32 ? run_tiled<float>(A, G, NT, p->blocks_per_cu, geom.lds, s)

@@ -42,6 +42,7 @@ struct TileArgs {
     int tiles_x, tiles_y, ntiles;
     int max_shells, inplace, ghost, tile_track, local_track;
     double eps, a, c;
+    double c2;        // < 0: no data term; else eqn:ready2's |g| > c2 until it leaves nothing ready
     LaunchSync sync;  // launch start-up (join words and epoch)
 };
 
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     __shared__ int s_tcnt[16];      // phase A: hole pixels per tile of a batch
     __shared__ int s_seg[kXcd];     // this pass's active-tile list length per XCD
     __shared__ int s_pf[kXcd];      // the pass's fills per XCD
+    __shared__ int s_km[kXcd];      // largest shell + 1 filled so far, per XCD
     __shared__ int s_nbhole[9];     // hole counts of the tile's 3 x 3 neighbourhood
 
     const int tid = threadIdx.x;
@@ -304,8 +306,13 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
     const int nG = NT / G;
     const int l = tid & (G - 1);
     const int wave_base = tid & ~63;
+    // eqn:ready2: the data term holds pixels back until a shell fills nothing;
+    // from that shell on (the next pass starts there) it is dropped, and that
+    // pass visits every tile with holes left, whose windows may now change
+    // although nothing near them was filled
+    bool phase1 = A.c2 >= 0.0, force_all = false;
+    int k0 = 0;  // first shell of the pass
     for (int p = 0; total_filled < total_hole; ++p) {
-        const int k0 = p * A.S;
         if (A.max_shells > 0 && k0 >= A.max_shells) break;
         const int Sp = A.max_shells > 0 ? min(A.S, A.max_shells - k0) : A.S;
         if (lw == 0 && tid < kXcd) {
@@ -320,15 +327,17 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         int32_t *nxt_act = ((p & 1) ? A.act0 : A.act1) + (long long)xcd * A.ntiles;
         int32_t *nxt_cnt = &ctl[xw(xcd, XF_ACT + (p + 1) % 3)];
         __syncthreads();  // s_seg holds this pass's list lengths
+        const bool listed = A.tile_track && !force_all;  // the pass visits the listed tiles
         int n_tiles_pass = A.ntiles;
-        if (A.tile_track) {
+        if (listed) {
             n_tiles_pass = 0;
 #pragma unroll
             for (int x = 0; x < kXcd; ++x) n_tiles_pass += s_seg[x];
         }
         for (int v = lw; v < n_tiles_pass; v += nblk) {
             int t = v;
-            if (A.tile_track) {
+            if (force_all && A.tile_track && A.t_rem[t] == 0) continue;  // no hole left in the tile
+            if (listed) {
                 int i = v, x = 0;
                 while (x < kXcd - 1 && i >= s_seg[x]) i -= s_seg[x++];
                 // a listed tile whose holes are all filled finds nothing to do; its
@@ -442,7 +451,9 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     const int Y = div_small(wi, WW, rWW), X = wi - Y * WW;
                     const float2 gv = gd[wi];
                     double val[4];
-                    const bool ok = fill_core<TS, G>(view, X, Y, (double)gv.x, (double)gv.y,
+                    // the data term of eqn:ready2 holds the pixel back (group-uniform)
+                    const bool ok = !(phase1 && !data_term_ok(gv, A.c2)) &&
+                                    fill_core<TS, G>(view, X, Y, (double)gv.x, (double)gv.y,
                                                      A.ghost != 0, s_off, s_rinv, T, Rb, j, l,
                                                      A.a, A.c, val);
                     if (l == 0) {
@@ -593,7 +604,6 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     for (int j = 0; j < Sp && j < 32; ++j) {
                         if (!s_front_in[j]) continue;
                         atomicAdd(&ctl[G_FRONT + (p & 1) * 32 + j], s_front_in[j]);
-                        if (A.front_hist && k0 + j < A.kcap) atomicAdd(&A.front_hist[k0 + j], s_front_in[j]);
                     }
                 }
                 if (tf && A.tile_track && tid < 9) {  // the 3 x 3 tile neighbourhood may change next pass
@@ -631,24 +641,42 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
         grid_sync(ctl, grid);
         GF_TACC(5);
         GF_TCNT(10, 1);
-        // this pass's fills and the next pass's list lengths, in one round trip
+        // this pass's fills, the shells filled so far and the next pass's list
+        // lengths, in one round trip
         if (tid < kXcd) {
             s_pf[tid] = ld_ctl(ctl, xw(tid, XF_PFILL + p % 3));
             if (A.tile_track) s_seg[tid] = ld_ctl(ctl, xw(tid, XF_ACT + (p + 1) % 3));
+            if (phase1) s_km[tid] = ld_ctl(ctl, xw(tid, XF_KMAX));
         }
         __syncthreads();
-        int fills = 0;
+        int fills = 0, km = 0;
 #pragma unroll
-        for (int x = 0; x < kXcd; ++x) fills += s_pf[x];
+        for (int x = 0; x < kXcd; ++x) {
+            fills += s_pf[x];
+            if (phase1) km = max(km, s_km[x]);
+        }
         if (lw == 0 && tid == 0) {  // front sizes of the pass; the half is reused two passes on
             for (int j = 0; j < Sp && j < 32; ++j) {
                 int32_t *cw = &ctl[G_FRONT + (p & 1) * 32 + j];
-                max_front = max(max_front, ld_ctl(ctl, G_FRONT + (p & 1) * 32 + j));
+                const int nf = ld_ctl(ctl, G_FRONT + (p & 1) * 32 + j);
+                max_front = max(max_front, nf);
+                if (A.front_hist && k0 + j < A.kcap) A.front_hist[k0 + j] = nf;  // a later pass may rewrite it
                 __hip_atomic_store(cw, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        force_all = false;
+        if (phase1 && km < k0 + Sp) {
+            // shell km filled nothing under the data term: it is taken again
+            // without it (nothing after it in this pass changed either)
+            phase1 = false;
+            force_all = true;
+            total_filled += fills;
+            k0 = km;
+            continue;
+        }
         if (fills == 0) break;
         total_filled += fills;
+        k0 += Sp;
     }
 
     // ---- finish ---------------------------------------------------------------

@@ -88,6 +88,13 @@ def test_bad_parameters_are_rejected(lib, field, value):
     assert _call(lib, p.c_struct()) == -1
 
 
+def test_data_term_needs_one_frame(lib):
+    import paper_1611_05319_amd as gf
+
+    assert _call(lib, gf.Params(c2=0.0).c_struct(), B=2) == -3
+    assert _call(lib, gf.Params(c2=float("nan")).c_struct()) == -1
+
+
 def test_tile_threads_only_with_the_tiled_engine(lib):
     import paper_1611_05319_amd as gf
 

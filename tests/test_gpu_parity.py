@@ -346,6 +346,41 @@ def test_smart_order_full_size(config):
             banner(f"smart order {config}: K={st['K']} worst rel err {worst:.2e}")
 
 
+def _guided_half(w):
+    """The frame with its guide kept on the left half of the hole only."""
+    img, lab, g = w.image[0], w.label[0], w.guide[0].copy()
+    g[:, g.shape[1] // 2:] = 0.0
+    return img, lab, g
+
+
+@pytest.mark.parametrize("c", [-1.0, 0.05])
+@pytest.mark.parametrize("c2", [0.0, 0.5])
+@pytest.mark.parametrize("engine", ENGINES)
+def test_data_term_ready2(engine, c2, c):
+    """eqn:ready2 (data term |g| > c2 until it leaves nothing ready, then
+    eqn:ready) on random problems with many zero guides, and on the
+    1920x1080 frame with the guide removed from its right half."""
+    rng = np.random.default_rng(int(c2 * 10) + (3 if c > 0 else 0))
+    for i in range(3):
+        img, lab, g = syn.random_tiny(rng, 70 + 9 * i, 90 - 7 * i, C=3, p_hole=0.45,
+                                      p_bystander=0.05, zero_guide_frac=0.4)
+        ref = oracle.fill(img, lab, g, c=c, c2=c2)
+        if c >= 0:
+            assert ref.n_ties == 0
+        for tracking in (True, False):
+            banner(f"ready2 random {i} c={c} c2={c2} engine={engine} tracking={tracking}")
+            _check(img, lab, g, c=c, c2=c2, tracking=tracking, ref=ref, **LAUNCH[engine])
+    w = syn.config2()
+    img, lab, g = _guided_half(w)
+    ref = oracle.fill(img, lab, g, eps=w.eps, mu=w.mu, c=c, c2=c2)
+    assert ref.n_ties == 0
+    banner(f"ready2 1920x1080 half guided c={c} c2={c2} engine={engine}")
+    ref, u, s, st, worst = _check(img, lab, g, eps=w.eps, mu=w.mu, c=c, c2=c2, ref=ref,
+                                  **LAUNCH[engine])
+    plain = oracle.fill(img, lab, g, eps=w.eps, mu=w.mu, c=c)
+    banner(f"ready2 1920x1080: K={st['K']} (without the data term {plain.K}), worst {worst:.2e}")
+
+
 def test_config3_full_size():
     w = syn.config3()
     ref = oracle.fill(w.image[0], w.label[0], w.guide[0], eps=5.0, mu=100.0)
