@@ -58,6 +58,9 @@ def _load():
                                                       ctypes.c_int, P, P, P, P, P, ctypes.c_int,
                                                       ctypes.c_int]
         lib.gfo_fill.restype = ctypes.c_int
+        lib.gfo_guide_field.argtypes = [ctypes.c_int] * 3 + [P, P, P, ctypes.c_double,
+                                                          ctypes.c_double, P]
+        lib.gfo_guide_field.restype = ctypes.c_int
         lib.gfo_adjoint.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_double, ctypes.c_double,
                                                          ctypes.c_int, P, P, P, P, P]
         lib.gfo_adjoint.restype = ctypes.c_int
@@ -175,6 +178,27 @@ def adjoint(label, guide, u_out, shell, grad_out, eps: float = 3.0, mu: float = 
     if squeeze:
         return gi[0], gg[0]
     return gi, gg
+
+
+def guide_field(label, seg, seg_off, eta: float = 3.0, cutoff: float | None = None):
+    """The guide field of Sec. 3.2 from polyline splines: label (B x) H x W;
+    seg: n x 6 (x0, y0, x1, y1, gx, gy) per segment; seg_off: B + 1 offsets of
+    each frame's segments; cutoff defaults to 3 eta.  Returns (B x) H x W x 2."""
+    lib = _load()
+    label = np.asarray(label)
+    squeeze = label.ndim == 2
+    lab = np.ascontiguousarray(label[None] if squeeze else label, dtype=np.uint8)
+    B, H, W = lab.shape
+    sg = np.ascontiguousarray(np.asarray(seg, dtype=np.float64).reshape(-1, 6))
+    so = np.ascontiguousarray(np.asarray(seg_off, dtype=np.int32))
+    if so.shape != (B + 1,) or so[-1] > sg.shape[0]:
+        raise ValueError("seg_off must hold B + 1 offsets into seg")
+    g = np.empty((B, H, W, 2), dtype=np.float64)
+    rc = lib.gfo_guide_field(B, H, W, _ptr(lab), _ptr(sg), _ptr(so), float(eta),
+                             float(3.0 * eta if cutoff is None else cutoff), _ptr(g))
+    if rc != 0:
+        raise ValueError(f"oracle guide field failed with code {rc}")
+    return g[0] if squeeze else g
 
 
 def offsets(eps: float):

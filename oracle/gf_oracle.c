@@ -533,3 +533,65 @@ int gfo_adjoint(int B, int H, int W, int C, const uint8_t *label, const double *
     free(G); free(rd); free(lam); free(v); free(u);
     return GFO_OK;
 }
+
+/*
+ * Guide field (Sec. 3.2): for every inpaint pixel x (label 1) of a frame,
+ * the spline Gamma_x nearest to x and
+ *     g(x) = g_Gamma_x exp(-d(x, Gamma_x)^2 / (2 eta^2)),
+ * set to 0 where d(x, Gamma_x) > cutoff (the paper cuts off at 3 eta); 0 on
+ * every other pixel and where the frame has no spline.  A spline is given as
+ * a polyline of segments, each segment carrying the direction g_Gamma of its
+ * spline (a straight spline has one segment; a sampled curve may give its
+ * segments the local tangent), so the spline nearest to x is the one holding
+ * the nearest segment.  Pixel (i, j) sits at the point (i, j): i the column,
+ * j the row.
+ *   seg      nseg*6: x0, y0, x1, y1, gx, gy of each segment
+ *   seg_off  B+1: the segments of frame b are seg_off[b] .. seg_off[b+1]-1
+ *   guide    B*H*W*2 output
+ * Distance to a segment: the foot of the perpendicular, clamped to the
+ * segment (the nearer end when it falls outside; the point itself for a
+ * segment of zero length).  Equal distances keep the first segment.
+ * Returns GFO_OK or GFO_EINVAL.
+ */
+int gfo_guide_field(int B, int H, int W, const uint8_t *label, const double *seg,
+                    const int32_t *seg_off, double eta, double cutoff, double *guide)
+{
+    if (B < 0 || H <= 0 || W <= 0 || !(eta > 0) || !(cutoff >= 0)) return GFO_EINVAL;
+    for (int b = 0; b < B; ++b) {
+        const int s0 = seg_off[b], s1 = seg_off[b + 1];
+        if (s0 < 0 || s1 < s0) return GFO_EINVAL;
+        for (int j = 0; j < H; ++j)
+            for (int i = 0; i < W; ++i) {
+                const size_t q = ((size_t)b * H + j) * W + i;
+                guide[2 * q] = 0.0;
+                guide[2 * q + 1] = 0.0;
+                if (label[q] != 1) continue;
+                double best = INFINITY;
+                int arg = -1;
+                for (int e = s0; e < s1; ++e) {
+                    const double *S = seg + 6 * (size_t)e;
+                    const double dx = S[2] - S[0], dy = S[3] - S[1];
+                    const double qx = (double)i - S[0], qy = (double)j - S[1];
+                    const double len2 = dx * dx + dy * dy;
+                    double t = 0.0;
+                    if (len2 > 0.0) {
+                        t = (qx * dx + qy * dy) / len2;
+                        if (t < 0.0) t = 0.0;
+                        if (t > 1.0) t = 1.0;
+                    }
+                    const double ex = qx - t * dx, ey = qy - t * dy;
+                    const double d2 = ex * ex + ey * ey;
+                    if (d2 < best) {
+                        best = d2;
+                        arg = e;
+                    }
+                }
+                if (arg < 0 || best > cutoff * cutoff) continue;
+                const double f = exp(-best / (2.0 * eta * eta));
+                guide[2 * q] = seg[6 * (size_t)arg + 4] * f;
+                guide[2 * q + 1] = seg[6 * (size_t)arg + 5] * f;
+            }
+    }
+    return GFO_OK;
+}
+

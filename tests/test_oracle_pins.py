@@ -464,3 +464,82 @@ def test_data_term_matches_set_transcription(seed):
     np.testing.assert_array_equal(np.array(ts, dtype=np.int32), r.shell)
     assert tK == r.K
     np.testing.assert_allclose(np.array(tu), r.u, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# the guide field (Sec. 3.2): g(x) = g_Gamma exp(-d(x, Gamma)^2 / (2 eta^2)) for
+# the spline nearest to x, 0 beyond the cutoff (3 eta) and off the hole
+
+
+def test_guide_field_straight_spline_closed_form():
+    H, W, eta = 40, 60, 3.0
+    lab = np.ones((H, W), np.uint8)
+    lab[:, :5] = 0
+    # one horizontal spline y = 20, x in [10, 50], direction (0.6, 0.8)
+    seg = np.array([[10.0, 20.0, 50.0, 20.0, 0.6, 0.8]])
+    g = oracle.guide_field(lab, seg, [0, 1], eta=eta)
+    for (i, j) in [(30, 20), (30, 23), (12, 11), (49, 29), (20, 14)]:
+        d = abs(j - 20)  # the foot of the perpendicular lies on the segment
+        f = math.exp(-d * d / (2 * eta * eta)) if d <= 3 * eta else 0.0
+        np.testing.assert_allclose(g[j, i], [0.6 * f, 0.8 * f], rtol=1e-15, atol=0)
+    # beyond an end the distance is to the end point
+    d2 = 4.0 ** 2 + 3.0 ** 2
+    np.testing.assert_allclose(g[23, 54], np.array([0.6, 0.8]) * math.exp(-d2 / 18.0), rtol=1e-15)
+    d2 = 7.0 ** 2 + 7.0 ** 2  # 9.9 px from the end: past the cutoff
+    np.testing.assert_array_equal(g[27, 57], [0.0, 0.0])
+    # exactly at the cutoff (9 px) the field is kept, one pixel further it is 0
+    np.testing.assert_allclose(g[29, 30], np.array([0.6, 0.8]) * math.exp(-81.0 / 18.0), rtol=1e-15)
+    np.testing.assert_array_equal(g[30, 30], [0.0, 0.0])
+    # pixels off the hole get 0
+    np.testing.assert_array_equal(g[20, 2], [0.0, 0.0])
+
+
+def test_guide_field_oblique_segment_and_nearest_spline():
+    H, W = 50, 50
+    lab = np.ones((H, W), np.uint8)
+    # segment from (10, 10) to (40, 40) (slope 1) and a vertical one at x = 30
+    seg = np.array([[10.0, 10.0, 40.0, 40.0, 1.0, 0.0],
+                    [30.0, 0.0, 30.0, 49.0, 0.0, 1.0]])
+    g = oracle.guide_field(lab, seg, [0, 2], eta=3.0)
+    # (20, 24): distance to the diagonal |20 - 24| / sqrt 2 = 2.83, to x = 30: 10
+    d = 4.0 / math.sqrt(2.0)
+    np.testing.assert_allclose(g[24, 20], [math.exp(-d * d / 18.0), 0.0], rtol=1e-14)
+    # (28, 10): diagonal 12.7 away, vertical 2 away
+    np.testing.assert_allclose(g[10, 28], [0.0, math.exp(-4.0 / 18.0)], rtol=1e-15)
+    # (35, 25): the diagonal is 10/sqrt 2 = 7.07 away, the vertical 5: the vertical wins
+    np.testing.assert_allclose(g[25, 35], [0.0, math.exp(-25.0 / 18.0)], rtol=1e-15)
+    # a pixel halfway between two parallel splines keeps the first
+    par = np.array([[0.0, 10.0, 49.0, 10.0, 1.0, 0.0], [0.0, 20.0, 49.0, 20.0, 0.0, 1.0]])
+    gp = oracle.guide_field(lab, par, [0, 2], eta=3.0)
+    np.testing.assert_allclose(gp[15, 25], [math.exp(-25.0 / 18.0), 0.0], rtol=1e-15)
+    np.testing.assert_allclose(gp[16, 25], [0.0, math.exp(-16.0 / 18.0)], rtol=1e-15)
+
+
+def test_guide_field_polyline_matches_point_distance_on_a_dense_curve():
+    # a circle of radius 15 as a 720-segment polyline: the distance of a pixel
+    # to it tends to |r - 15|
+    H = W = 60
+    lab = np.ones((H, W), np.uint8)
+    th = np.linspace(0, 2 * math.pi, 721)
+    cx = cy = 30.0
+    pts = np.stack([cx + 15 * np.cos(th), cy + 15 * np.sin(th)], -1)
+    seg = np.concatenate([pts[:-1], pts[1:], np.tile([[0.0, 1.0]], (720, 1))], axis=1)
+    g = oracle.guide_field(lab, seg, [0, 720], eta=3.0)
+    yy, xx = np.mgrid[0:H, 0:W]
+    r = np.hypot(xx - cx, yy - cy)
+    ref = np.where(np.abs(r - 15) <= 9.0, np.exp(-(r - 15) ** 2 / 18.0), 0.0)
+    near = np.abs(np.abs(r - 15) - 9.0) > 0.05  # away from the cutoff ring
+    np.testing.assert_allclose(g[..., 1][near], ref[near], atol=2e-3)
+    np.testing.assert_array_equal(g[..., 0], 0.0)
+
+
+def test_guide_field_frames_and_empty_lists():
+    lab = np.ones((3, 10, 12), np.uint8)
+    seg = np.array([[0.0, 5.0, 11.0, 5.0, 1.0, 0.0], [6.0, 0.0, 6.0, 9.0, 0.0, 1.0]])
+    g = oracle.guide_field(lab, seg, [0, 1, 1, 2])
+    assert (g[0, ..., 1] == 0).all() and (g[0, ..., 0] > 0).all()
+    assert (g[1] == 0).all()  # no spline in frame 1
+    assert (g[2, ..., 0] == 0).all() and (g[2, ..., 1] > 0).all()
+    # a zero-length segment measures the distance to its point
+    g0 = oracle.guide_field(lab[0], np.array([[4.0, 4.0, 4.0, 4.0, 0.0, 2.0]]), [0, 1])
+    np.testing.assert_allclose(g0[7, 8], [0.0, 2.0 * math.exp(-25.0 / 18.0)], rtol=1e-15)
