@@ -49,18 +49,22 @@ def algorithmic_bytes(B, H, W, C, elem, n_hole, inplace=False):
     return px * (C * elem + 1 + C * elem + 4) + n_hole * 8
 
 
+# the headers that hold the device code of the fill and adjoint kernels
+FILL_KERNEL_SOURCES = ("device_common.h", "fill_core.h", "global_engine.h", "tile_engine.h")
+
+
 def kernel_source_digest():
-    """SHA-256 over the HIP sources (sorted by name): a recorded HBM traffic
-    figure is valid only for the kernel build it was measured on."""
+    """SHA-256 over the fill and adjoint kernels' device sources (in the order
+    above): a recorded HBM traffic figure is valid only for the kernel code it
+    was measured on (the launch shape is recorded beside it)."""
     import hashlib
 
     d = os.path.join(ROOT, "paper_1611_05319_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".h", ".hip")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in FILL_KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 

@@ -213,6 +213,30 @@ size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const
  */
 gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p, int32_t *out6);
 
+/*
+ * Guide field (Sec. 3.2), the fill's input g built on the device: for every
+ * inpaint pixel x (label 1) the spline nearest to x and
+ *     g(x) = g_Gamma exp(-d(x, Gamma)^2 / (2 eta^2)),
+ * 0 where d(x, Gamma) > cutoff (the paper takes eta = 3 px and cutoff = 3 eta)
+ * or the frame has no spline, and 0 on every other pixel.  Splines are
+ * polylines: each segment carries its spline's direction g_Gamma (a straight
+ * spline is one segment; a sampled curve may give each segment the local
+ * tangent); the nearest spline is the one holding the nearest segment, equal
+ * distances keeping the first.  Pixel (i, j) sits at (i, j), i the column.
+ * Distances and the choice of spline are FP64; g is rounded to binary32.
+ *   label    B*H*W uint8 (device).
+ *   seg      device float32, nseg * 6: x0, y0, x1, y1, gx, gy per segment
+ *            (may be NULL when every frame has none).
+ *   seg_off  device int32[B + 1]: frame b's segments are seg_off[b] ..
+ *            seg_off[b + 1] - 1 (non-decreasing, within seg).
+ *   guide    device float32, B*H*W*2 output (gx, gy), every pixel written.
+ * Returns GF_OK or GF_EINVAL (bad size, eta <= 0, cutoff < 0, null
+ * pointer) / GF_EDEVICE; asynchronous on `stream`.
+ */
+gf_status gf_guide_field(int B, int H, int W, const uint8_t *label, const float *seg,
+                         const int32_t *seg_off, double eta, double cutoff, float *guide,
+                         void *stream);
+
 /* Text for a status code (static storage). */
 const char *gf_status_string(gf_status s);
 

@@ -24,6 +24,7 @@ import torch
 
 __all__ = [
     "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_batched_noalloc",
+    "guide_field",
     "fill_backward", "GuidefillFn",
     "library_path", "load", "stats_fields", "tile_geometry", "ENGINE_TILED", "ENGINE_FRONT",
 ]
@@ -108,6 +109,8 @@ def load():
         lib.gf_fill_batched.restype = I
         lib.gf_fill_batched_noalloc.argtypes = [P, P, I, I, I, I, I, P, P, PP, P, P, P, P, P, I, P]
         lib.gf_fill_batched_noalloc.restype = I
+        lib.gf_guide_field.argtypes = [I, I, I, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
+        lib.gf_guide_field.restype = I
         lib.gf_fill.argtypes = [P, P, I, I, I, I, P, P, PP, P, P, P, Z, P]
         lib.gf_fill.restype = I
         lib.gf_fill_backward.argtypes = [P, P, I, I, I, I, I, P, P, P, I, PP, P, P, P, Z, P]
@@ -295,6 +298,36 @@ def fill_batched_noalloc(img: torch.Tensor, label: torch.Tensor, guide: torch.Te
                                      None, None, 0, ctypes.c_void_p(s.cuda_stream))
     _check(rc, "gf_fill_batched_noalloc")
     return FillResult(out, shell, stats)
+
+
+def guide_field(label: torch.Tensor, seg: torch.Tensor, seg_off: torch.Tensor, eta: float = 3.0,
+                cutoff: float | None = None, out: torch.Tensor | None = None,
+                check_offsets: bool = True) -> torch.Tensor:
+    """gf_guide_field: the guide field of Sec. 3.2 from polyline splines.
+    label: (B x) H x W uint8; seg: n x 6 float32 (x0, y0, x1, y1, gx, gy);
+    seg_off: B + 1 int32 offsets of each frame's segments; cutoff defaults to
+    3 eta.  Returns (B x) H x W x 2 float32.  check_offsets reads seg_off back
+    to the host to validate it before the launch."""
+    squeeze = label.dim() == 2
+    lab = label.unsqueeze(0) if squeeze else label
+    dev = _require_device(lab, seg, seg_off)
+    if seg.dtype != torch.float32 or seg_off.dtype != torch.int32 or lab.dtype != torch.uint8:
+        raise TypeError("seg float32, seg_off int32, label uint8")
+    B, H, W = lab.shape
+    if seg_off.numel() != B + 1 or seg.dim() != 2 or seg.shape[1] != 6:
+        raise ValueError("seg must be n x 6 and seg_off hold B + 1 offsets")
+    if check_offsets:  # one device-to-host copy of B + 1 integers
+        so = seg_off.cpu()
+        if int(so[0]) < 0 or bool((so[1:] < so[:-1]).any()) or int(so[-1]) > seg.shape[0]:
+            raise ValueError("seg_off must be non-decreasing offsets into seg")
+    if out is None:
+        out = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
+    lib = load()
+    rc = lib.gf_guide_field(B, H, W, _ptr(lab), _ptr(seg) if seg.numel() else None, _ptr(seg_off),
+                            float(eta), float(3.0 * eta if cutoff is None else cutoff), _ptr(out),
+                            _stream_ptr(dev))
+    _check(rc, "gf_guide_field")
+    return out[0] if squeeze else out
 
 
 def fill(img: torch.Tensor, label: torch.Tensor, guide: torch.Tensor,

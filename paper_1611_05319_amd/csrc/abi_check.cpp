@@ -6,6 +6,7 @@
 // arguments that are rejected before any kernel launch (so it is safe with
 // or without a device), and checks the documented results.  Exit status 0
 // when every check holds.
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -30,6 +31,7 @@ static gf_params defaults() {
     p.c = -1.0;
     p.ghost = 1;
     p.tracking = 1;
+    p.c2 = -1.0;
     return p;
 }
 
@@ -112,6 +114,11 @@ int main() {
     p.tile_threads = 640;
     CHECK(fill(p, 1, 8, 8, 3, 0, fake, 1 << 20, fake) == GF_EINVAL);
     p = defaults();
+    p.c2 = 0.0;  // the data term's phase switch needs one frame
+    CHECK(fill(p, 2, 8, 8, 3, 0, fake, 1 << 20, fake) == GF_EUNSUPPORTED);
+    p.c2 = NAN;
+    CHECK(fill(p, 1, 8, 8, 3, 0, fake, 1 << 20, fake) == GF_EINVAL);
+    p = defaults();
     CHECK(gf_fill(fake, fake, 8, 8, 3, GF_F32, (const uint8_t *)fake, (const float *)fake, &p,
                   (int32_t *)fake, (int32_t *)fake, fake, 16, nullptr) == GF_EINVAL);
 
@@ -135,6 +142,15 @@ int main() {
                            (float *)fake, (float *)fake, fake, nb, nullptr) == GF_EINVAL);
     CHECK(gf_fill_backward(fg, fake, 1, 8, 8, 3, GF_F32, nullptr, fg, (const int32_t *)fake, 2, &p,
                            (float *)fake, (float *)fake, fake, nb - 256, nullptr) == GF_EINVAL);
+
+    // the guide field
+    const uint8_t *fl = (const uint8_t *)fake;
+    const float *fs = (const float *)fake;
+    const int32_t *fo = (const int32_t *)fake;
+    CHECK(gf_guide_field(0, 8, 8, fl, fs, fo, 3.0, 9.0, (float *)fake, nullptr) == GF_EINVAL);
+    CHECK(gf_guide_field(1, 8, 8, fl, fs, fo, 0.0, 9.0, (float *)fake, nullptr) == GF_EINVAL);
+    CHECK(gf_guide_field(1, 8, 8, fl, fs, fo, 3.0, -1.0, (float *)fake, nullptr) == GF_EINVAL);
+    CHECK(gf_guide_field(1, 8, 8, fl, fs, nullptr, 3.0, 9.0, (float *)fake, nullptr) == GF_EINVAL);
 
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);

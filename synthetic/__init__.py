@@ -17,7 +17,9 @@ thin disocclusion "cracks" next to object silhouettes):
   (Catmull-Rom tangents) dilated by one pixel, discs, wiggly straight bands;
 * guidance: the unit tangent of the nearest of several open cubic splines when
   within 15 px, else the structure-tensor direction tanh((l+ - l-)/Lambda) v-
-  of the unmasked image (sigma = 2, rho = 4, Lambda = 1e-5), zero off the hole.
+  of the unmasked image (sigma = 2, rho = 4, Lambda = 1e-5), zero off the hole;
+  the same random splines as polylines (segments with unit chord directions)
+  are the input of the guide-field construction.
 
 Array conventions: images are H x W x C (row, column, channel); a guide vector
 is (gx, gy) with gx along columns and gy along rows.
@@ -38,6 +40,8 @@ __all__ = [
     "band_mask_c1",
     "silhouette_bands",
     "spline_guidance",
+    "spline_segments",
+    "pack_segments",
     "config1",
     "config2",
     "config3",
@@ -308,6 +312,34 @@ def spline_guidance(rng, img: np.ndarray, label: np.ndarray, n_splines: int = 6,
         g = np.where(close, t, g)
     g = np.where((label == 1)[..., None], g, 0.0)
     return g.astype(np.float32)
+
+
+def spline_segments(rng, H: int, W: int, n_splines: int = 6, spacing: float = 2.0) -> np.ndarray:
+    """Random open cubic Beziers between border points (as drawn for
+    spline_guidance), each sampled every `spacing` px of control-polygon
+    length and returned as a polyline: n x 6 float32 rows (x0, y0, x1, y1, gx,
+    gy), (gx, gy) the unit chord direction of the segment."""
+    rows = []
+    for _ in range(n_splines):
+        p, _t = _open_spline(rng, H, W, spacing=spacing)
+        d = p[1:] - p[:-1]
+        n = np.linalg.norm(d, axis=1)
+        keep = n > 0
+        d = d[keep] / n[keep, None]
+        rows.append(np.concatenate([p[:-1][keep], p[1:][keep], d], axis=1))
+    if not rows:
+        return np.zeros((0, 6), dtype=np.float32)
+    return np.concatenate(rows).astype(np.float32)
+
+
+def pack_segments(frames) -> tuple[np.ndarray, np.ndarray]:
+    """Concatenate per-frame segment arrays into (seg n x 6 float32, seg_off
+    int32[B + 1])."""
+    frames = [np.asarray(f, dtype=np.float32).reshape(-1, 6) for f in frames]
+    off = np.zeros(len(frames) + 1, dtype=np.int32)
+    off[1:] = np.cumsum([len(f) for f in frames])
+    seg = np.concatenate(frames) if frames else np.zeros((0, 6), dtype=np.float32)
+    return np.ascontiguousarray(seg, dtype=np.float32), off
 
 
 def constant_guidance(H: int, W: int, angle_deg: float, label: np.ndarray) -> np.ndarray:

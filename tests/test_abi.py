@@ -211,3 +211,14 @@ def test_noalloc_rejects_requests_beyond_the_scratch(lib):
     bad = gf.Params(eps=0.5).c_struct()
     assert lib.gf_fill_batched_noalloc(fake, fake, 1, 8, 8, 3, 0, fake, fake, ctypes.byref(bad),
                                        fake, fake, None, None, None, 0, None) == -1
+
+
+def test_guide_field_rejects_bad_arguments(lib):
+    fake = ctypes.c_void_p(1 << 20)
+    for B, H, W, eta, cutoff in [(0, 8, 8, 3.0, 9.0), (1, 0, 8, 3.0, 9.0), (1, 8, 8, 0.0, 9.0),
+                                 (1, 8, 8, 3.0, -1.0), (1, 8, 8, float("nan"), 9.0),
+                                 (1, 8, 8, 3.0, float("inf"))]:
+        assert lib.gf_guide_field(B, H, W, fake, fake, fake, eta, cutoff, fake, None) == -1
+    assert lib.gf_guide_field(1, 8, 8, None, fake, fake, 3.0, 9.0, fake, None) == -1
+    assert lib.gf_guide_field(1, 8, 8, fake, fake, None, 3.0, 9.0, fake, None) == -1
+    assert lib.gf_guide_field(1, 8, 8, fake, fake, fake, 3.0, 9.0, None, None) == -1
