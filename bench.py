@@ -81,11 +81,12 @@ def launch_key(p, H, W, C):
     return f"engine=1 group={p.group} blocks_per_cu={p.blocks_per_cu}"
 
 
-def recorded_traffic(params, H, W, C):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when it
-    is missing, was taken on other kernel sources or another launch shape."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2_1080p.md")
+def recorded_traffic(params, H, W, C, summary="traffic_c2_1080p.md"):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    under profiles/ (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None
+    when it is missing, was taken on other kernel sources or another launch
+    shape."""
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         with open(path) as f:
             rec = dict(line.split(":", 1) for line in f.read().splitlines()
@@ -387,7 +388,10 @@ def main():
                           "batched_speedup": round(wall_s / wall_b, 3),
                           "mpix_filled_per_s": round(st4["filled"] / (wall_b * 1e-3) / 1e6, 2),
                           "hbm_gbs": round(nb4 / (ev_b * 1e-3) / 1e9, 1),
-                          "hbm_frac": round(nb4 / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                          "hbm_frac": round(nb4 / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "algorithmic_bytes": nb4,
+                          "traffic": recorded_traffic(p4, *i4.shape[1:],
+                                                      summary="traffic_c4_batched.md")}
         del i4, l4, g4, plan_b, plans_1
         # deep front: 3840x2160, one 200-px band plus 20 discs, eps = 5, mu = 100
         out["deep_front"] = deep_front(w3, torch, gf, autotune, dev, args)
@@ -416,7 +420,9 @@ def main():
                                       "field, eps=3, mu=50",
                           "launch": launch_fields(p5),
                           "fwd_ms": round(wall_f, 4), "fwd_bwd_ms": round(wall_fb, 4),
-                          "ratio": round(wall_fb / wall_f, 3), "shells": K5}
+                          "ratio": round(wall_fb / wall_f, 3), "shells": K5,
+                          "bwd_traffic": recorded_traffic(p5, *i5.shape[1:],
+                                                          summary="traffic_c5_grad.md")}
     print(json.dumps(out), flush=True)
 
 
