@@ -10,6 +10,9 @@ the paper it takes).
 ball of ghost pixels, Sec. 3.1 and 3.3) or the coherence-transport lattice
 ball, the weights of eqn:weight and onion or smart order (eqn:confidence,
 eqn:ready).  `adjoint` is the reverse-mode derivative of that fill.
+`guide_field` builds g from polyline splines (Sec. 3.2); `coherence_fill`
+is the coherence-transport comparison mode, g re-estimated before every
+shell from the modified structure tensor (eqn:modStructureTensor).
 `tiny` holds an independent pure-Python transcription for small domains.
 """
 
@@ -21,6 +24,7 @@ import subprocess
 import threading
 
 import numpy as np
+from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gf_oracle.c")
@@ -64,6 +68,13 @@ def _load():
         lib.gfo_adjoint.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_double, ctypes.c_double,
                                                          ctypes.c_int, P, P, P, P, P]
         lib.gfo_adjoint.restype = ctypes.c_int
+        lib.gfo_mod_structure_tensor.argtypes = [ctypes.c_int] * 3 + [P, P, ctypes.c_double,
+                                                                      ctypes.c_double, P]
+        lib.gfo_mod_structure_tensor.restype = ctypes.c_int
+        lib.gfo_tensor_guide.argtypes = [P, ctypes.c_double, P]
+        lib.gfo_tensor_guide.restype = None
+        lib.gfo_coherence_guide.argtypes = [ctypes.c_int] * 4 + [P, P] + [ctypes.c_double] * 3 + [P]
+        lib.gfo_coherence_guide.restype = ctypes.c_int
         lib.gfo_offsets.argtypes = [ctypes.c_double, P, P, ctypes.c_int]
         lib.gfo_offsets.restype = ctypes.c_int
         lib.gfo_round_f16.argtypes = [ctypes.c_double]
@@ -199,6 +210,114 @@ def guide_field(label, seg, seg_off, eta: float = 3.0, cutoff: float | None = No
     if rc != 0:
         raise ValueError(f"oracle guide field failed with code {rc}")
     return g[0] if squeeze else g
+
+
+def mod_structure_tensor(u, known, sigma: float = 2.0, rho: float = 4.0):
+    """The modified structure tensor of eqn:modStructureTensor over the known
+    set `known` (H x W bool) of u (H x W x C): H x W x 3 (Jxx, Jxy, Jyy), NaN
+    where no known pixel lies within the rho window."""
+    lib = _load()
+    u = np.asarray(u, dtype=np.float64)
+    if u.ndim == 2:
+        u = u[..., None]
+    H, W, C = u.shape
+    uu = np.ascontiguousarray(u)
+    kn = np.ascontiguousarray(np.asarray(known, dtype=bool).astype(np.uint8))
+    if kn.shape != (H, W):
+        raise ValueError("known must be H x W")
+    J = np.empty((H, W, 3), dtype=np.float64)
+    rc = lib.gfo_mod_structure_tensor(H, W, C, _ptr(uu), _ptr(kn), float(sigma), float(rho), _ptr(J))
+    if rc != 0:
+        raise ValueError(f"oracle structure tensor failed with code {rc}")
+    return J
+
+
+def tensor_guide(J, Lambda: float = 1e-5):
+    """tanh((l+ - l-) / Lambda) v- of each tensor in J (... x 3), sign fixed
+    so that gx > 0 (or gx == 0 and gy > 0); 0 for NaN tensors."""
+    lib = _load()
+    J = np.asarray(J, dtype=np.float64)
+    flat = np.ascontiguousarray(J.reshape(-1, 3))
+    g = np.zeros((flat.shape[0], 2), dtype=np.float64)
+    one = np.empty(2, dtype=np.float64)
+    for e in range(flat.shape[0]):
+        row = np.ascontiguousarray(flat[e])
+        lib.gfo_tensor_guide(_ptr(row), float(Lambda), _ptr(one))
+        g[e] = one
+    return g.reshape(J.shape[:-1] + (2,))
+
+
+def coherence_guide(u, label, sigma: float = 2.0, rho: float = 4.0, Lambda: float = 1e-5):
+    """The comparison mode's guide for the current state: on every label-1
+    pixel the coherence direction of the modified structure tensor over the
+    label-0 pixels; 0 elsewhere.  u: (B x) H x W x C; label: (B x) H x W."""
+    lib = _load()
+    label = np.asarray(label)
+    squeeze = label.ndim == 2
+    lab = np.ascontiguousarray(label[None] if squeeze else label, dtype=np.uint8)
+    uu = np.asarray(u, dtype=np.float64)
+    uu = np.ascontiguousarray(uu[None] if squeeze else uu)
+    B, H, W = lab.shape
+    C = uu.shape[-1]
+    if uu.shape != (B, H, W, C):
+        raise ValueError("shape mismatch")
+    g = np.empty((B, H, W, 2), dtype=np.float64)
+    rc = lib.gfo_coherence_guide(B, H, W, C, _ptr(uu), _ptr(lab), float(sigma), float(rho),
+                                 float(Lambda), _ptr(g))
+    if rc != 0:
+        raise ValueError(f"oracle coherence guide failed with code {rc}")
+    return g[0] if squeeze else g
+
+
+@dataclass
+class CoherenceResult:
+    u: np.ndarray        # B x H x W x C
+    shell: np.ndarray    # B x H x W: -1 readable, -2 bystander, k filled at shell k, -3 never
+    guide: np.ndarray    # B x H x W x 2: the guide each pixel was filled with (0 elsewhere)
+    K: int               # shells that filled at least one pixel
+    frame_K: list
+
+
+def coherence_fill(img, label, eps: float = 3.0, mu: float = 50.0, sigma: float = 2.0,
+                   rho: float = 4.0, Lambda: float = 1e-5, c: float = -1.0, ghost: bool = False,
+                   max_shells: int = 0, storage: str = "f64", threads: int | None = None):
+    """The coherence-transport comparison mode (Sec. 3.2): before every shell
+    the guide of each inpaint pixel is re-estimated from the modified
+    structure tensor of the current known set, then one shell of Algorithm 1
+    runs with it (lattice ball by default).  Returns a CoherenceResult."""
+    img = np.asarray(img)
+    label = np.asarray(label)
+    squeeze = label.ndim == 2
+    u = np.array(img[None] if squeeze else img, dtype=np.float64)
+    lab = np.array(label[None] if squeeze else label, dtype=np.uint8)
+    B, H, W = lab.shape
+    shell = np.where(lab == 0, -1, np.where(lab == 2, -2, -3)).astype(np.int32)
+    used = np.zeros((B, H, W, 2), dtype=np.float64)
+    frame_K = [0] * B
+    k = 0
+    while max_shells <= 0 or k < max_shells:
+        if not (lab == 1).any():
+            break
+        g = coherence_guide(u, lab, sigma, rho, Lambda)
+        r = fill(u, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, max_shells=1, storage=storage,
+                 threads=threads)
+        rs = r.shell if r.shell.ndim == 3 else r.shell[None]
+        new = (lab == 1) & (rs == 0)
+        if not new.any():
+            break
+        ru = r.u if r.u.ndim == 4 else r.u[None]
+        u = np.array(ru)
+        shell[new] = k
+        used[new] = g[new]
+        lab[new] = 0
+        for f in range(B):
+            if new[f].any():
+                frame_K[f] += 1
+        k += 1
+    res = CoherenceResult(u, shell, used, k, frame_K)
+    if squeeze:
+        res = CoherenceResult(u[0], shell[0], used[0], k, frame_K)
+    return res
 
 
 def offsets(eps: float):

@@ -45,6 +45,12 @@
  *    region's last pixel, or an earlier one if the rest of the region cannot
  *    be reached), and that shell is then evaluated with eqn:ready.
  *
+ *  - Guide field (Sec. 3.2): g = g_Gamma exp(-d^2 / (2 eta^2)) from the
+ *    nearest polyline spline, 0 beyond the cutoff (gfo_guide_field).
+ *  - Comparison mode (Sec. 3.2, eqn:modStructureTensor): the modified
+ *    structure tensor of the current known set and the coherence direction
+ *    it gives (gfo_mod_structure_tensor, gfo_coherence_guide).
+ *
  * Readings where the paper is silent (the same list is kept with the design
  * notes): (0,0) is not in the ball; R acts with the unit vector g/|g|; the
  * ball boundary n^2+m^2 <= eps^2 is inclusive; ghost points outside the image
@@ -595,3 +601,171 @@ int gfo_guide_field(int B, int H, int W, const uint8_t *label, const double *seg
     return GFO_OK;
 }
 
+
+/* ------------------------------------------------------------------------
+ * Modified structure tensor of coherence transport (Sec. 3.2,
+ * eqn:modStructureTensor) and the guide it gives, for the comparison mode in
+ * which g is re-estimated on the current known set at every shell.
+ *
+ * With K = the known set (Omega minus D^(k) and B), g_s the Gaussian of
+ * variance s^2 truncated to |dx|, |dy| <= floor(2 s) (the (4 s + 1)^2 window
+ * of Sec. 3.2; its normalisation cancels in both quotients):
+ *   v(p)  = sum_q g_sigma(q - p) 1_K(q) u(q) / sum_q g_sigma(q - p) 1_K(q),
+ *           defined where the denominator is positive;
+ *   T(p)  = sum over channels of grad v (x) grad v, at p in K, with grad v by
+ *           central differences (one-sided where a neighbour is outside the
+ *           image or v is undefined there, 0 if both are);
+ *   J(x)  = sum_p g_rho(p - x) 1_K(p) T(p) / sum_p g_rho(p - x) 1_K(p),
+ *           NaN where the denominator is 0.
+ * Sums run over in-image pixels, rows outer, columns inner.
+ */
+static double gauss2(int dx, int dy, double s)
+{
+    return exp(-(double)(dx * dx + dy * dy) / (2.0 * s * s));
+}
+
+int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t *known,
+                             double sigma, double rho, double *J)
+{
+    if (H <= 0 || W <= 0 || C <= 0 || !(sigma > 0) || !(rho > 0)) return GFO_EINVAL;
+    const int rs = (int)floor(2.0 * sigma), rr = (int)floor(2.0 * rho);
+    const size_t HW = (size_t)H * W;
+    double *v = (double *)malloc(HW * C * sizeof(double));
+    unsigned char *vok = (unsigned char *)malloc(HW);
+    double *T = (double *)malloc(HW * 3 * sizeof(double));
+    if (!v || !vok || !T) {
+        free(v); free(vok); free(T);
+        return GFO_ENOMEM;
+    }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t p = (size_t)j * W + i;
+            double den = 0.0;
+            for (int c = 0; c < C; ++c) v[p * C + c] = 0.0;
+            for (int dy = -rs; dy <= rs; ++dy)
+                for (int dx = -rs; dx <= rs; ++dx) {
+                    const int qi = i + dx, qj = j + dy;
+                    if (qi < 0 || qi >= W || qj < 0 || qj >= H) continue;
+                    const size_t q = (size_t)qj * W + qi;
+                    if (!known[q]) continue;
+                    const double w = gauss2(dx, dy, sigma);
+                    den += w;
+                    for (int c = 0; c < C; ++c) v[p * C + c] += w * u[q * C + c];
+                }
+            vok[p] = den > 0.0;
+            for (int c = 0; c < C; ++c) v[p * C + c] = den > 0.0 ? v[p * C + c] / den : 0.0;
+        }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t p = (size_t)j * W + i;
+            T[3 * p] = T[3 * p + 1] = T[3 * p + 2] = 0.0;
+            if (!known[p]) continue;
+            const int l = i > 0 && vok[p - 1], r = i < W - 1 && vok[p + 1];
+            const int t = j > 0 && vok[p - W], b = j < H - 1 && vok[p + W];
+            for (int c = 0; c < C; ++c) {
+                double gx = 0.0, gy = 0.0;
+                if (l && r) gx = (v[(p + 1) * C + c] - v[(p - 1) * C + c]) / 2.0;
+                else if (r) gx = v[(p + 1) * C + c] - v[p * C + c];
+                else if (l) gx = v[p * C + c] - v[(p - 1) * C + c];
+                if (t && b) gy = (v[(p + W) * C + c] - v[(p - W) * C + c]) / 2.0;
+                else if (b) gy = v[(p + W) * C + c] - v[p * C + c];
+                else if (t) gy = v[p * C + c] - v[(p - W) * C + c];
+                T[3 * p] += gx * gx;
+                T[3 * p + 1] += gx * gy;
+                T[3 * p + 2] += gy * gy;
+            }
+        }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            const size_t x = (size_t)j * W + i;
+            double den = 0.0, a = 0.0, b = 0.0, c = 0.0;
+            for (int dy = -rr; dy <= rr; ++dy)
+                for (int dx = -rr; dx <= rr; ++dx) {
+                    const int qi = i + dx, qj = j + dy;
+                    if (qi < 0 || qi >= W || qj < 0 || qj >= H) continue;
+                    const size_t q = (size_t)qj * W + qi;
+                    if (!known[q]) continue;
+                    const double w = gauss2(dx, dy, rho);
+                    den += w;
+                    a += w * T[3 * q];
+                    b += w * T[3 * q + 1];
+                    c += w * T[3 * q + 2];
+                }
+            if (den > 0.0) {
+                J[3 * x] = a / den;
+                J[3 * x + 1] = b / den;
+                J[3 * x + 2] = c / den;
+            } else {
+                J[3 * x] = J[3 * x + 1] = J[3 * x + 2] = NAN;
+            }
+        }
+    free(v); free(vok); free(T);
+    return GFO_OK;
+}
+
+/* The coherence direction of a structure tensor (a, b; b, c) as a guide:
+ * g = tanh((lambda+ - lambda-) / Lambda) v-, v- the unit eigenvector of the
+ * smaller eigenvalue (Sec. 3.2, with the tensor in place of J at x_base).
+ * With h = (a - c)/2 and r = sqrt(h^2 + b^2), lambda+ - lambda- = 2 r and v-
+ * is along (b, -(h + r)) when h >= 0, else along (h - r, b).  Its sign (which
+ * the fill does not see) is fixed so that gx > 0, or gx == 0 and gy > 0.  A
+ * NaN tensor (no known pixel within reach) gives g = 0. */
+void gfo_tensor_guide(const double *J, double Lambda, double *g)
+{
+    g[0] = g[1] = 0.0;
+    const double a = J[0], b = J[1], c = J[2];
+    if (isnan(a) || isnan(b) || isnan(c)) return;
+    const double h = (a - c) / 2.0;
+    const double r = sqrt(h * h + b * b);
+    if (!(r > 0.0)) return;
+    double vx, vy;
+    if (h >= 0.0) {
+        vx = b;
+        vy = -(h + r);
+    } else {
+        vx = h - r;
+        vy = b;
+    }
+    const double n = sqrt(vx * vx + vy * vy);
+    vx /= n;
+    vy /= n;
+    if (vx < 0.0 || (vx == 0.0 && vy < 0.0)) {
+        vx = -vx;
+        vy = -vy;
+    }
+    const double m = tanh(2.0 * r / Lambda);
+    g[0] = m * vx;
+    g[1] = m * vy;
+}
+
+/* The comparison mode's guide at shell k for B frames: for every inpaint
+ * pixel (label 1) of each frame, the coherence direction of the modified
+ * structure tensor over the known set label == 0; 0 on every other pixel. */
+int gfo_coherence_guide(int B, int H, int W, int C, const double *u, const uint8_t *label,
+                        double sigma, double rho, double Lambda, double *guide)
+{
+    if (B < 0 || H <= 0 || W <= 0 || C <= 0 || !(Lambda > 0)) return GFO_EINVAL;
+    const size_t HW = (size_t)H * W;
+    unsigned char *known = (unsigned char *)malloc(HW);
+    double *J = (double *)malloc(HW * 3 * sizeof(double));
+    if (!known || !J) {
+        free(known); free(J);
+        return GFO_ENOMEM;
+    }
+    for (int f = 0; f < B; ++f) {
+        const uint8_t *lab = label + (size_t)f * HW;
+        for (size_t p = 0; p < HW; ++p) known[p] = lab[p] == 0;
+        const int rc = gfo_mod_structure_tensor(H, W, C, u + (size_t)f * HW * C, known, sigma, rho, J);
+        if (rc != GFO_OK) {
+            free(known); free(J);
+            return rc;
+        }
+        double *gf = guide + (size_t)f * HW * 2;
+        for (size_t p = 0; p < HW; ++p) {
+            gf[2 * p] = gf[2 * p + 1] = 0.0;
+            if (lab[p] == 1) gfo_tensor_guide(J + 3 * p, Lambda, gf + 2 * p);
+        }
+    }
+    free(known); free(J);
+    return GFO_OK;
+}

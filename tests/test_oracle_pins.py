@@ -543,3 +543,123 @@ def test_guide_field_frames_and_empty_lists():
     # a zero-length segment measures the distance to its point
     g0 = oracle.guide_field(lab[0], np.array([[4.0, 4.0, 4.0, 4.0, 0.0, 2.0]]), [0, 1])
     np.testing.assert_allclose(g0[7, 8], [0.0, 2.0 * math.exp(-25.0 / 18.0)], rtol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# the modified structure tensor and the coherence-transport comparison mode
+
+
+def _orientation(g):
+    """Angle of the line along g with the horizontal, y pointing up, in [0, 180)."""
+    return math.degrees(math.atan2(-g[1], g[0])) % 180.0
+
+
+def _kink_problem(N=81):
+    """Sec. 3.2's kinking example: above the hole (the lower half plane) white
+    below the line y = x and grey above it; pixels on the line half way."""
+    c0 = N // 2
+    rows, cols = np.mgrid[0:N, 0:N]
+    X, Y = cols - c0, c0 - rows
+    u = np.where(Y < X, 1.0, 0.5)
+    u = np.where(Y == X, 0.75, u)[..., None]
+    return u, Y >= 0, c0
+
+
+def test_mod_structure_tensor_reads_the_kinked_angle():
+    """sigma = 2, rho = 4: on the boundary of the hole, on the line, the
+    modified tensor reads 57 degrees (the paper's value, printed to the
+    degree; the discrete reading here gives 57.6); well inside the known half
+    plane it reads the true 45."""
+    u, known, c0 = _kink_problem()
+    J = oracle.mod_structure_tensor(u, known, 2.0, 4.0)
+    a = _orientation(oracle.tensor_guide(J[c0 + 1, c0 - 1]))   # A: first hole row, on the line
+    b = _orientation(oracle.tensor_guide(J[c0 - 20, c0 + 20]))  # B: 20 px inside the known part
+    assert abs(a - 57.0) <= 1.0, a
+    assert abs(b - 45.0) <= 1e-9, b
+    # with nothing missing, the tensor at A is the ordinary one: 45 degrees
+    J_all = oracle.mod_structure_tensor(u, np.ones_like(known), 2.0, 4.0)
+    assert abs(_orientation(oracle.tensor_guide(J_all[c0 + 1, c0 - 1])) - 45.0) <= 1e-9
+
+
+def test_mod_structure_tensor_of_a_linear_ramp():
+    """Away from the frame border a Gaussian average of an affine image is the
+    image itself and central differences are exact, so the tensor is
+    sum_c grad u_c (x) grad u_c and the guide is tanh(|grad u|^2 / Lambda)
+    times the unit vector along the isophote."""
+    H, W = 40, 52
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    grads = [(0.013, -0.021), (-0.004, 0.009)]
+    u = np.stack([a * x + b * y + 0.3 for a, b in grads], axis=-1)
+    J = oracle.mod_structure_tensor(u, np.ones((H, W), bool), 2.0, 4.0)
+    want = np.array([sum(a * a for a, _ in grads), sum(a * b for a, b in grads),
+                     sum(b * b for _, b in grads)])
+    inner = J[13:H - 13, 13:W - 13]
+    np.testing.assert_allclose(inner, np.broadcast_to(want, inner.shape), rtol=1e-9, atol=1e-15)
+    # one channel: lambda- = 0, lambda+ = |grad u|^2, v- perpendicular to grad u
+    a, b = grads[0]
+    J1 = oracle.mod_structure_tensor(u[..., :1], np.ones((H, W), bool), 2.0, 4.0)
+    g = oracle.tensor_guide(J1[20, 26], Lambda=1e-3)
+    n2 = a * a + b * b
+    perp = np.array([-b, a]) / math.sqrt(n2)
+    perp = perp if perp[0] > 0 else -perp
+    np.testing.assert_allclose(g, math.tanh(n2 / 1e-3) * perp, rtol=1e-9, atol=1e-12)
+
+
+def test_mod_structure_tensor_ignores_the_hole_and_is_transpose_covariant():
+    rng = np.random.default_rng(31)
+    H, W = 30, 34
+    u = rng.uniform(size=(H, W, 2))
+    known = rng.uniform(size=(H, W)) > 0.3
+    J = oracle.mod_structure_tensor(u, known, 1.5, 3.0)
+    # colours of unknown pixels do not enter
+    u2 = u.copy()
+    u2[~known] = rng.uniform(size=((~known).sum(), 2)) * 7.0
+    np.testing.assert_array_equal(oracle.mod_structure_tensor(u2, known, 1.5, 3.0), J)
+    # transposing the image swaps Jxx and Jyy
+    Jt = oracle.mod_structure_tensor(u.transpose(1, 0, 2), known.T, 1.5, 3.0)
+    np.testing.assert_allclose(Jt.transpose(1, 0, 2)[..., ::-1], J, rtol=1e-12, atol=1e-15)
+    # a constant image has no orientation (0.5: every weighted mean is exact)
+    Jc = oracle.mod_structure_tensor(np.full((H, W, 1), 0.5), known, 1.5, 3.0)
+    assert np.nanmax(np.abs(Jc)) == 0.0
+    assert (oracle.tensor_guide(Jc) == 0.0).all()
+
+
+def test_mod_structure_tensor_undefined_far_from_known_pixels():
+    H, W = 41, 41
+    known = np.ones((H, W), bool)
+    known[5:36, 5:36] = False           # 31 x 31 hole; rho = 4 reaches 8 px
+    J = oracle.mod_structure_tensor(np.zeros((H, W, 1)), known, 2.0, 4.0)
+    assert np.isnan(J[20, 20]).all() and not np.isnan(J[12, 20]).any()
+    assert (oracle.tensor_guide(J[20, 20]) == 0.0).all()
+    lab = np.where(known, 0, 1).astype(np.uint8)
+    g = oracle.coherence_guide(np.zeros((H, W, 1)), lab)
+    assert (g[20, 20] == 0.0).all()
+
+
+def test_coherence_fill_continues_a_vertical_edge_exactly():
+    """A vertical edge above a horizontal band hole: v depends on x alone
+    (the Gaussian is separable and the known set depends on y alone), so the
+    tensor is diag(v_x^2, 0) up to rounding, the guide vertical at every
+    shell, and the fill reproduces each column's colour."""
+    H, W = 48, 64
+    u = np.where(np.arange(W) < 30, 1.0, 0.5)[None, :, None].repeat(H, 0)
+    img = u.copy()
+    lab = np.zeros((H, W), np.uint8)
+    lab[20:30] = 1
+    img[20:30] = 0.0
+    r = oracle.coherence_fill(img, lab, eps=3.0, mu=50.0)
+    np.testing.assert_allclose(r.u, u, rtol=0, atol=1e-12)
+    used = r.guide[lab == 1]
+    assert np.abs(used[:, 0]).max() <= 1e-12 * np.abs(used[:, 1]).max()  # rounding only
+    near = r.guide[20:30, 26:34]        # columns whose window sees the edge
+    assert (np.abs(near[..., 1]) > 0.99).all()
+
+
+def test_coherence_fill_shells_are_the_lattice_onion_shells():
+    """With the lattice ball and onion order the shells do not depend on g,
+    so the comparison mode's shell map is the plain fill's (ghost off)."""
+    img, lab, g = _random_problem(17, H=40, W=44)
+    r = oracle.coherence_fill(img, lab, eps=3.0, mu=50.0)
+    ref = oracle.fill(img, lab, g, eps=3.0, mu=50.0, ghost=False)
+    np.testing.assert_array_equal(r.shell, ref.shell)
+    assert r.K == ref.K
