@@ -214,6 +214,47 @@ size_t gf_backward_workspace_size(int B, int H, int W, int C, gf_dtype dt, const
 gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p, int32_t *out6);
 
 /*
+ * Coherence-transport comparison mode (Sec. 3.2, eqn:modStructureTensor):
+ * the fill of Algorithm 1 in which, before every shell, each front pixel x
+ * (label 1 with a known in-frame 8-neighbour) takes as its guide the
+ * coherence direction of the modified structure tensor of the pixels known
+ * at that shell (label 0 and the pixels filled so far):
+ *   v = (g_sigma * (1_K u)) / (g_sigma * 1_K),
+ *   J = (g_rho * (1_K sum_c grad v_c (x) grad v_c)) / (g_rho * 1_K),
+ *   g(x) = tanh((lambda+ - lambda-) / Lambda) v-  (0 where no known pixel
+ *   lies within the rho window),
+ * Gaussians of variance sigma^2 and rho^2 truncated to |dx|, |dy| <= floor(2 s),
+ * grad v by central differences (one-sided at the frame edge).  This is the
+ * direction estimate the paper shows to kink lines (its Sec. 3.2 example);
+ * Guidefill itself uses splines (gf_guide_field).  With p->ghost = 0 the
+ * neighbourhood is coherence transport's lattice ball.  The tensor and g are
+ * computed in FP64 from the stored colours; the fill as in gf_fill_batched.
+ *   img_in / img_out, label, shell_out: as for gf_fill_batched (img_out may
+ *               alias img_in); stats: int32[8 + 4*B] device array in the
+ *               gf_fill_batched layout (K, filled, hole, largest front,
+ *               label errors, per-frame K, filled, hole).
+ *   sigma, rho  the two scales (> 0; the paper's example takes 2 and 4;
+ *               sigma <= 8, rho <= 16).  lambda: Lambda > 0 (1e-5 in the
+ *               paper).
+ *   guide_used  nullable, device float32 B*H*W*2: the guide each filled
+ *               pixel was filled with (0 elsewhere); sign as computed
+ *               (gx > 0, or gx == 0 and gy > 0).
+ *   p           as for gf_fill_batched; p->max_shells bounds the shells;
+ *               p->c2 must be < 0 (GF_EUNSUPPORTED otherwise).
+ * Workspace: gf_coherence_workspace_size bytes, zeroed before first use.
+ * Unlike the other fills this call is synchronous: it reads each shell's
+ * count back to the host to decide whether to go on (one stream
+ * synchronisation per shell), and returns when the fill has finished.
+ */
+size_t gf_coherence_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
+
+gf_status gf_fill_coherence(const void *img_in, void *img_out, int B, int H, int W, int C,
+                            gf_dtype dt, const uint8_t *label, const gf_params *p,
+                            double sigma, double rho, double lambda, int32_t *shell_out,
+                            int32_t *stats, float *guide_used, void *workspace, size_t ws_bytes,
+                            void *stream);
+
+/*
  * Guide field (Sec. 3.2), the fill's input g built on the device: for every
  * inpaint pixel x (label 1) the spline nearest to x and
  *     g(x) = g_Gamma exp(-d(x, Gamma)^2 / (2 eta^2)),

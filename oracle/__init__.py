@@ -68,7 +68,7 @@ def _load():
         lib.gfo_adjoint.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_double, ctypes.c_double,
                                                          ctypes.c_int, P, P, P, P, P]
         lib.gfo_adjoint.restype = ctypes.c_int
-        lib.gfo_mod_structure_tensor.argtypes = [ctypes.c_int] * 3 + [P, P, ctypes.c_double,
+        lib.gfo_mod_structure_tensor.argtypes = [ctypes.c_int] * 3 + [P, P, P, ctypes.c_double,
                                                                       ctypes.c_double, P]
         lib.gfo_mod_structure_tensor.restype = ctypes.c_int
         lib.gfo_tensor_guide.argtypes = [P, ctypes.c_double, P]
@@ -226,7 +226,8 @@ def mod_structure_tensor(u, known, sigma: float = 2.0, rho: float = 4.0):
     if kn.shape != (H, W):
         raise ValueError("known must be H x W")
     J = np.empty((H, W, 3), dtype=np.float64)
-    rc = lib.gfo_mod_structure_tensor(H, W, C, _ptr(uu), _ptr(kn), float(sigma), float(rho), _ptr(J))
+    rc = lib.gfo_mod_structure_tensor(H, W, C, _ptr(uu), _ptr(kn), None, float(sigma), float(rho),
+                                      _ptr(J))
     if rc != 0:
         raise ValueError(f"oracle structure tensor failed with code {rc}")
     return J
@@ -280,11 +281,14 @@ class CoherenceResult:
 
 def coherence_fill(img, label, eps: float = 3.0, mu: float = 50.0, sigma: float = 2.0,
                    rho: float = 4.0, Lambda: float = 1e-5, c: float = -1.0, ghost: bool = False,
-                   max_shells: int = 0, storage: str = "f64", threads: int | None = None):
+                   max_shells: int = 0, storage: str = "f64", guide_f32: bool = False,
+                   threads: int | None = None):
     """The coherence-transport comparison mode (Sec. 3.2): before every shell
     the guide of each inpaint pixel is re-estimated from the modified
     structure tensor of the current known set, then one shell of Algorithm 1
-    runs with it (lattice ball by default).  Returns a CoherenceResult."""
+    runs with it (lattice ball by default).  `guide_f32` rounds each guide to
+    binary32 before the fill uses it (the fill's guide input type).
+    Returns a CoherenceResult."""
     img = np.asarray(img)
     label = np.asarray(label)
     squeeze = label.ndim == 2
@@ -299,6 +303,8 @@ def coherence_fill(img, label, eps: float = 3.0, mu: float = 50.0, sigma: float 
         if not (lab == 1).any():
             break
         g = coherence_guide(u, lab, sigma, rho, Lambda)
+        if guide_f32:
+            g = g.astype(np.float32).astype(np.float64)
         r = fill(u, lab, g, eps=eps, mu=mu, c=c, ghost=ghost, max_shells=1, storage=storage,
                  threads=threads)
         rs = r.shell if r.shell.ndim == 3 else r.shell[None]

@@ -616,7 +616,8 @@ int gfo_guide_field(int B, int H, int W, const uint8_t *label, const double *seg
  *           central differences (one-sided where a neighbour is outside the
  *           image or v is undefined there, 0 if both are);
  *   J(x)  = sum_p g_rho(p - x) 1_K(p) T(p) / sum_p g_rho(p - x) 1_K(p),
- *           NaN where the denominator is 0.
+ *           NaN where the denominator is 0 (and, when `want` is given, at
+ *           the pixels it does not ask for).
  * Sums run over in-image pixels, rows outer, columns inner.
  */
 static double gauss2(int dx, int dy, double s)
@@ -625,7 +626,7 @@ static double gauss2(int dx, int dy, double s)
 }
 
 int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t *known,
-                             double sigma, double rho, double *J)
+                             const uint8_t *want, double sigma, double rho, double *J)
 {
     if (H <= 0 || W <= 0 || C <= 0 || !(sigma > 0) || !(rho > 0)) return GFO_EINVAL;
     const int rs = (int)floor(2.0 * sigma), rr = (int)floor(2.0 * rho);
@@ -637,6 +638,7 @@ int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t
         free(v); free(vok); free(T);
         return GFO_ENOMEM;
     }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t p = (size_t)j * W + i;
@@ -655,6 +657,7 @@ int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t
             vok[p] = den > 0.0;
             for (int c = 0; c < C; ++c) v[p * C + c] = den > 0.0 ? v[p * C + c] / den : 0.0;
         }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t p = (size_t)j * W + i;
@@ -675,9 +678,14 @@ int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t
                 T[3 * p + 2] += gy * gy;
             }
         }
+#pragma omp parallel for schedule(dynamic, 4)
     for (int j = 0; j < H; ++j)
         for (int i = 0; i < W; ++i) {
             const size_t x = (size_t)j * W + i;
+            if (want && !want[x]) {
+                J[3 * x] = J[3 * x + 1] = J[3 * x + 2] = NAN;
+                continue;
+            }
             double den = 0.0, a = 0.0, b = 0.0, c = 0.0;
             for (int dy = -rr; dy <= rr; ++dy)
                 for (int dx = -rr; dx <= rr; ++dx) {
@@ -747,17 +755,22 @@ int gfo_coherence_guide(int B, int H, int W, int C, const double *u, const uint8
     if (B < 0 || H <= 0 || W <= 0 || C <= 0 || !(Lambda > 0)) return GFO_EINVAL;
     const size_t HW = (size_t)H * W;
     unsigned char *known = (unsigned char *)malloc(HW);
+    unsigned char *want = (unsigned char *)malloc(HW);
     double *J = (double *)malloc(HW * 3 * sizeof(double));
-    if (!known || !J) {
-        free(known); free(J);
+    if (!known || !want || !J) {
+        free(known); free(want); free(J);
         return GFO_ENOMEM;
     }
     for (int f = 0; f < B; ++f) {
         const uint8_t *lab = label + (size_t)f * HW;
-        for (size_t p = 0; p < HW; ++p) known[p] = lab[p] == 0;
-        const int rc = gfo_mod_structure_tensor(H, W, C, u + (size_t)f * HW * C, known, sigma, rho, J);
+        for (size_t p = 0; p < HW; ++p) {
+            known[p] = lab[p] == 0;
+            want[p] = lab[p] == 1;
+        }
+        const int rc =
+            gfo_mod_structure_tensor(H, W, C, u + (size_t)f * HW * C, known, want, sigma, rho, J);
         if (rc != GFO_OK) {
-            free(known); free(J);
+            free(known); free(want); free(J);
             return rc;
         }
         double *gf = guide + (size_t)f * HW * 2;
@@ -766,6 +779,6 @@ int gfo_coherence_guide(int B, int H, int W, int C, const double *u, const uint8
             if (lab[p] == 1) gfo_tensor_guide(J + 3 * p, Lambda, gf + 2 * p);
         }
     }
-    free(known); free(J);
+    free(known); free(want); free(J);
     return GFO_OK;
 }

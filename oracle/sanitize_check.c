@@ -28,6 +28,13 @@ int gfo_adjoint(int B, int H, int W, int C, const uint8_t *label, const double *
                 double eps, double mu, int ghost, const double *u_out, const int32_t *shell,
                 const double *grad_out, double *grad_in, double *grad_g);
 
+int gfo_mod_structure_tensor(int H, int W, int C, const double *u, const uint8_t *known,
+                             const uint8_t *want, double sigma, double rho, double *J);
+int gfo_coherence_guide(int B, int H, int W, int C, const double *u, const uint8_t *label,
+                        double sigma, double rho, double Lambda, double *guide);
+int gfo_guide_field(int B, int H, int W, const uint8_t *label, const double *seg,
+                    const int32_t *seg_off, double eta, double cutoff, double *guide);
+
 static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
 
 static uint64_t next_u64(void)
@@ -142,6 +149,31 @@ int main(void)
     run_case(3, 8, 8, 3, 0.0, 0.2, 3.0, 50.0, -1.0, 1, 0, 0, -1.0);
     /* a hole enclosed by bystanders stalls */
     run_case(1, 16, 16, 3, 0.3, 0.6, 3.0, 50.0, -1.0, 1, 0, 0, 0.0);
+    /* the modified structure tensor, the comparison mode's guide and the
+       guide field, on frames of several shapes including 1 x n and n x 1 */
+    const int shapes[][3] = {{1, 1, 1}, {1, 17, 3}, {9, 1, 2}, {13, 19, 3}, {24, 20, 4}};
+    for (int e = 0; e < 5; ++e) {
+        const int H = shapes[e][0], W = shapes[e][1], C = shapes[e][2];
+        const size_t HW = (size_t)H * W;
+        double *u = (double *)malloc(2 * HW * C * sizeof(double));
+        uint8_t *lab = (uint8_t *)malloc(2 * HW);
+        double *J = (double *)malloc(HW * 3 * sizeof(double));
+        double *g = (double *)malloc(2 * HW * 2 * sizeof(double));
+        for (size_t i = 0; i < 2 * HW * C; ++i) u[i] = uniform();
+        for (size_t i = 0; i < 2 * HW; ++i) {
+            const double r = uniform();
+            lab[i] = (uint8_t)(r < 0.4 ? 1 : (r < 0.5 ? 2 : 0));
+        }
+        uint8_t *known = (uint8_t *)malloc(HW);
+        for (size_t i = 0; i < HW; ++i) known[i] = lab[i] == 0;
+        CHECK(gfo_mod_structure_tensor(H, W, C, u, known, lab, 2.0, 4.0, J) == 0, "tensor %dx%d", H, W);
+        CHECK(gfo_mod_structure_tensor(H, W, C, u, known, NULL, 0.3, 1.0, J) == 0, "tensor %dx%d", H, W);
+        CHECK(gfo_coherence_guide(2, H, W, C, u, lab, 1.5, 3.0, 1e-5, g) == 0, "coherence %dx%d", H, W);
+        const double seg[12] = {0.0, 0.0, W - 1.0, H - 1.0, 0.6, 0.8, 2.0, 2.0, 2.0, 2.0, 1.0, 0.0};
+        const int32_t off[3] = {0, 2, 2};
+        CHECK(gfo_guide_field(2, H, W, lab, seg, off, 3.0, 9.0, g) == 0, "guide field %dx%d", H, W);
+        free(u); free(lab); free(J); free(g); free(known);
+    }
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);
         return 1;

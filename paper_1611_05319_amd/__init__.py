@@ -24,7 +24,7 @@ import torch
 
 __all__ = [
     "Params", "FillResult", "FillPlan", "BackwardPlan", "fill", "fill_batched", "fill_batched_noalloc",
-    "guide_field",
+    "guide_field", "fill_coherence", "CoherenceResult",
     "fill_backward", "GuidefillFn",
     "library_path", "load", "stats_fields", "tile_geometry", "ENGINE_TILED", "ENGINE_FRONT",
 ]
@@ -109,6 +109,11 @@ def load():
         lib.gf_fill_batched.restype = I
         lib.gf_fill_batched_noalloc.argtypes = [P, P, I, I, I, I, I, P, P, PP, P, P, P, P, P, I, P]
         lib.gf_fill_batched_noalloc.restype = I
+        lib.gf_coherence_workspace_size.argtypes = [I, I, I, I, I, P]
+        lib.gf_coherence_workspace_size.restype = Z
+        D = ctypes.c_double
+        lib.gf_fill_coherence.argtypes = [P, P, I, I, I, I, I, P, P, D, D, D, P, P, P, P, Z, P]
+        lib.gf_fill_coherence.restype = I
         lib.gf_guide_field.argtypes = [I, I, I, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
         lib.gf_guide_field.restype = I
         lib.gf_fill.argtypes = [P, P, I, I, I, I, P, P, PP, P, P, P, Z, P]
@@ -298,6 +303,51 @@ def fill_batched_noalloc(img: torch.Tensor, label: torch.Tensor, guide: torch.Te
                                      None, None, 0, ctypes.c_void_p(s.cuda_stream))
     _check(rc, "gf_fill_batched_noalloc")
     return FillResult(out, shell, stats)
+
+
+@dataclass
+class CoherenceResult:
+    out: torch.Tensor          # (B x) H x W x C filled image
+    shell: torch.Tensor        # (B x) H x W int32 shell map
+    stats: torch.Tensor        # int32 stats (gf_fill_batched layout)
+    guide_used: torch.Tensor | None  # (B x) H x W x 2: the guide each pixel was filled with
+
+
+def fill_coherence(img: torch.Tensor, label: torch.Tensor, params: Params | None = None,
+                   sigma: float = 2.0, rho: float = 4.0, Lambda: float = 1e-5,
+                   out: torch.Tensor | None = None, want_guide: bool = True,
+                   workspace: Workspace | None = None) -> CoherenceResult:
+    """gf_fill_coherence: the coherence-transport comparison mode (the guide
+    re-estimated before every shell from the modified structure tensor of the
+    known pixels).  params default to the lattice ball (ghost off).  The call
+    returns when the fill has finished (one host read-back per shell)."""
+    squeeze = img.dim() == 3
+    im = img.unsqueeze(0) if squeeze else img
+    lab = label.unsqueeze(0) if squeeze else label
+    dev = _require_device(im, lab)
+    B, H, W, C = im.shape
+    if lab.shape != (B, H, W) or lab.dtype != torch.uint8:
+        raise ValueError("label must be (B x) H x W uint8")
+    p = params if params is not None else Params(ghost=False)
+    pc = p.c_struct()
+    dt = _dtype_code(im)
+    lib = load()
+    need = lib.gf_coherence_workspace_size(B, H, W, C, dt, ctypes.byref(pc))
+    if need == 0:
+        raise RuntimeError(f"gf_coherence_workspace_size rejected the request: {lib.gf_last_error().decode()}")
+    ws = workspace if workspace is not None else Workspace()
+    buf = ws.get(need, dev)
+    o = out if out is not None else torch.empty_like(im)
+    shell = torch.empty((B, H, W), dtype=torch.int32, device=dev)
+    stats = torch.empty(STAT_FRAME0 + STAT_PER_FRAME * B, dtype=torch.int32, device=dev)
+    gu = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev) if want_guide else None
+    rc = lib.gf_fill_coherence(_ptr(im), _ptr(o), B, H, W, C, dt, _ptr(lab), ctypes.byref(pc),
+                               float(sigma), float(rho), float(Lambda), _ptr(shell), _ptr(stats),
+                               _ptr(gu), _ptr(buf), need, _stream_ptr(dev))
+    _check(rc, "gf_fill_coherence")
+    if squeeze:
+        return CoherenceResult(o[0], shell[0], stats, gu[0] if gu is not None else None)
+    return CoherenceResult(o, shell, stats, gu)
 
 
 def guide_field(label: torch.Tensor, seg: torch.Tensor, seg_off: torch.Tensor, eta: float = 3.0,

@@ -143,6 +143,23 @@ int main() {
     CHECK(gf_fill_backward(fg, fake, 1, 8, 8, 3, GF_F32, nullptr, fg, (const int32_t *)fake, 2, &p,
                            (float *)fake, (float *)fake, fake, nb - 256, nullptr) == GF_EINVAL);
 
+    // the comparison fill
+    p = defaults();
+    p.ghost = 0;
+    const size_t nc = gf_coherence_workspace_size(2, 40, 50, 3, GF_F32, &p);
+    CHECK(nc > 0 && nc % 256 == 0);
+    CHECK(gf_coherence_workspace_size(0, 40, 50, 3, GF_F32, &p) == 0);
+    int32_t *fi = (int32_t *)fake;
+    CHECK(gf_fill_coherence(fake, fake, 2, 40, 50, 3, GF_F32, (const uint8_t *)fake, &p, 0.0, 4.0,
+                            1e-5, fi, fi, nullptr, fake, nc, nullptr) == GF_EINVAL);
+    CHECK(gf_fill_coherence(fake, fake, 2, 40, 50, 3, GF_F32, (const uint8_t *)fake, &p, 2.0, 17.0,
+                            1e-5, fi, fi, nullptr, fake, nc, nullptr) == GF_EUNSUPPORTED);
+    CHECK(gf_fill_coherence(fake, fake, 2, 40, 50, 3, GF_F32, (const uint8_t *)fake, &p, 2.0, 4.0,
+                            1e-5, fi, fi, nullptr, fake, nc - 256, nullptr) == GF_EINVAL);
+    p.c2 = 0.5;
+    CHECK(gf_fill_coherence(fake, fake, 1, 40, 50, 3, GF_F32, (const uint8_t *)fake, &p, 2.0, 4.0,
+                            1e-5, fi, fi, nullptr, fake, nc, nullptr) == GF_EUNSUPPORTED);
+
     // the guide field
     const uint8_t *fl = (const uint8_t *)fake;
     const float *fs = (const float *)fake;

@@ -28,8 +28,10 @@
 
 #include <chrono>
 #include <mutex>
+#include <vector>
 #include <unordered_map>
 
+#include "coherence.h"
 #include "guide_field.h"
 #include "guidefill.h"
 #include "tile_engine.h"
@@ -621,9 +623,180 @@ gf_status fill_batched(const void *img_in, void *img_out, int B, int H, int W, i
     return rc;
 }
 
+// Workspace of the comparison fill: the per-shell fill's workspace first
+// (it keeps its launch handshake state across calls), then working labels,
+// guides, the per-shell shell map and stats.
+struct CtLayout {
+    size_t fill, label, guide, step, stats, bad, total;
+};
+
+bool ct_layout(int B, int H, int W, int C, int dt, const gf_params *p, CtLayout &L) {
+    gf_params p1 = *p;
+    p1.max_shells = 1;
+    const size_t fw = workspace_bytes(B, H, W, C, dt, &p1);
+    if (fw == 0) return false;
+    const size_t np = (size_t)B * H * W;
+    size_t off = 0;
+    L.fill = off; off += align256(fw);
+    L.label = off; off += align256(np);
+    L.guide = off; off += align256(np * 2 * sizeof(float));
+    L.step = off; off += align256(np * sizeof(int32_t));
+    L.stats = off; off += align256((size_t)(GF_STAT_FRAME0 + GF_STAT_PER_FRAME * B) * sizeof(int32_t));
+    L.bad = off; off += 256;
+    L.total = off;
+    return true;
+}
+
+// Tile edge of the tensor kernel: 16 when its LDS fits, else 8 (0: neither)
+int ct_tile(int rs, int rr, int C, size_t lds_limit) {
+    if (ct_lds(16, rs, rr, C).total <= lds_limit) return 16;
+    if (ct_lds(8, rs, rr, C).total <= lds_limit) return 8;
+    return 0;
+}
+
+gf_status ct_validate(const gf_params *p, int B, int H, int W, int C, int dt, double sigma,
+                      double rho, double lambda) {
+    gf_status st = validate(p, B, H, W, C, dt);
+    if (st != GF_OK) return st;
+    if (!(sigma > 0.0) || !(rho > 0.0) || !(lambda > 0.0) || !isfinite(lambda)) return GF_EINVAL;
+    if (!(sigma <= 8.0) || !(rho <= 16.0)) return GF_EUNSUPPORTED;
+    // the guide changes every shell, so the data term's phase switch has no fixed region
+    if (p->c2 >= 0.0) return GF_EUNSUPPORTED;
+    return GF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t gf_coherence_workspace_size(int B, int H, int W, int C, gf_dtype dt_arg, const gf_params *p) {
+    const int dt = raw_enum(&dt_arg);
+    if (!p || validate(p, B, H, W, C, dt) != GF_OK) return 0;
+    CtLayout L;
+    if (!ct_layout(B, H, W, C, dt, p, L)) return 0;
+    return L.total;
+}
+
+gf_status gf_fill_coherence(const void *img_in, void *img_out, int B, int H, int W, int C,
+                            gf_dtype dt_arg, const uint8_t *label, const gf_params *p,
+                            double sigma, double rho, double lambda, int32_t *shell_out,
+                            int32_t *stats, float *guide_used, void *workspace, size_t ws_bytes,
+                            void *stream) {
+    const int dt = raw_enum(&dt_arg);
+    gf_status st = ct_validate(p, B, H, W, C, dt, sigma, rho, lambda);
+    if (st != GF_OK) return st;
+    if (!img_in || !img_out || !label || !shell_out || !stats || !workspace) return GF_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return GF_EINVAL;
+    CtLayout L;
+    if (!ct_layout(B, H, W, C, dt, p, L)) return GF_EINVAL;
+    if (ws_bytes < L.total) return GF_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_err("hipGetDevice", e); return GF_EDEVICE; }
+    const DevInfo di = device_info(dev);
+    const int rs = (int)floor(2.0 * sigma), rr = (int)floor(2.0 * rho);
+    const int tile = ct_tile(rs, rr, C, di.lds_block);
+    if (tile == 0) return GF_EUNSUPPORTED;
+    const size_t lds = ct_lds(tile, rs, rr, C).total;
+    const void *kfn = dt == GF_F32 ? reinterpret_cast<const void *>(ct_guide_kernel<float>)
+                                   : reinterpret_cast<const void *>(ct_guide_kernel<__half>);
+    cached_occupancy(dev, kfn, kBlock, lds, &e);
+    if (e != hipSuccess) { set_err("tensor kernel set-up", e); return GF_EDEVICE; }
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *ws = reinterpret_cast<char *>(workspace);
+    uint8_t *label_w = reinterpret_cast<uint8_t *>(ws + L.label);
+    float *guide_w = reinterpret_cast<float *>(ws + L.guide);
+    int32_t *step = reinterpret_cast<int32_t *>(ws + L.step);
+    int32_t *stats_step = reinterpret_cast<int32_t *>(ws + L.stats);
+    int32_t *bad = reinterpret_cast<int32_t *>(ws + L.bad);
+    const long long NP = (long long)B * H * W;
+    const size_t esz = dt == GF_F32 ? 4 : 2;
+    const int nstat = GF_STAT_FRAME0 + GF_STAT_PER_FRAME * B;
+    const int egrid = (int)std::min<long long>((NP + kBlock - 1) / kBlock, 8192);
+
+    if (img_out != img_in) {
+        e = hipMemcpyAsync(img_out, img_in, (size_t)NP * C * esz, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) { set_err("hipMemcpyAsync", e); return GF_EDEVICE; }
+    }
+    e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) { set_err("hipMemsetAsync", e); return GF_EDEVICE; }
+    hipLaunchKernelGGL(ct_init_kernel, dim3(egrid), dim3(kBlock), 0, s, label, label_w, shell_out,
+                       guide_w, guide_used, bad, NP);
+    e = hipGetLastError();
+    if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
+
+    CtArgs A;
+    A.img = img_out;
+    A.label = label_w;
+    A.guide = guide_w;
+    A.HW = (long long)H * W;
+    A.B = B;
+    A.H = H;
+    A.W = W;
+    A.C = C;
+    A.tile = tile;
+    A.tiles_x = (W + tile - 1) / tile;
+    A.tiles_y = (H + tile - 1) / tile;
+    A.rs = rs;
+    A.rr = rr;
+    A.sigma = sigma;
+    A.rho = rho;
+    A.lambda = lambda;
+    const long long ngrid = (long long)B * A.tiles_x * A.tiles_y;
+    if (ngrid >= (1ll << 31)) return GF_EUNSUPPORTED;
+
+    gf_params p1 = *p;
+    p1.max_shells = 1;
+    std::vector<int32_t> step_stats(nstat), total(nstat, 0);
+    int k = 0;
+    for (;;) {
+        if (p->max_shells > 0 && k >= p->max_shells) break;
+        void *kargs[] = {&A};
+        e = hipLaunchKernel(kfn, dim3((unsigned)ngrid), dim3(kBlock), kargs, lds, s);
+        if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
+        st = fill_batched(img_out, img_out, B, H, W, C, dt, label_w, guide_w, &p1, step, stats_step,
+                          nullptr, nullptr, nullptr, 0, ws + L.fill, L.label - L.fill, stream);
+        if (st != GF_OK) return st;
+        hipLaunchKernelGGL(ct_commit_kernel, dim3(egrid), dim3(kBlock), 0, s, label_w, step,
+                           shell_out, guide_w, guide_used, NP, k);
+        e = hipGetLastError();
+        if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
+        e = hipMemcpyAsync(step_stats.data(), stats_step, nstat * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { set_err("shell statistics", e); return GF_EDEVICE; }
+        if (k == 0) {
+            total[GF_STAT_HOLE] = step_stats[GF_STAT_HOLE];
+            total[GF_STAT_WORKGROUPS] = step_stats[GF_STAT_WORKGROUPS];
+            for (int f = 0; f < B; ++f)
+                total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2] =
+                    step_stats[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2];
+        }
+        total[GF_STAT_SYNC_TIMEOUT] |= step_stats[GF_STAT_SYNC_TIMEOUT];
+        total[GF_STAT_MAX_FRONT] = std::max(total[GF_STAT_MAX_FRONT], step_stats[GF_STAT_MAX_FRONT]);
+        const int filled = step_stats[GF_STAT_FILLED];
+        if (filled == 0) break;
+        total[GF_STAT_FILLED] += filled;
+        total[GF_STAT_SHELLS] = k + 1;
+        for (int f = 0; f < B; ++f) {
+            const int ff = step_stats[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1];
+            total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f] += ff > 0 ? 1 : 0;
+            total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1] += ff;
+        }
+        ++k;
+        if (total[GF_STAT_FILLED] >= total[GF_STAT_HOLE]) break;
+    }
+    int32_t nbad = 0;
+    e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_err("label check", e); return GF_EDEVICE; }
+    total[GF_STAT_LABEL_ERR] = nbad;
+    e = hipMemcpyAsync(stats, total.data(), nstat * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_err("statistics", e); return GF_EDEVICE; }
+    return GF_OK;
+}
 
 gf_status gf_fill_batched_noalloc(const void *img_in, void *img_out, int B, int H, int W, int C,
                                   gf_dtype dt_arg, const uint8_t *label, const float *guide,

@@ -222,3 +222,29 @@ def test_guide_field_rejects_bad_arguments(lib):
     assert lib.gf_guide_field(1, 8, 8, None, fake, fake, 3.0, 9.0, fake, None) == -1
     assert lib.gf_guide_field(1, 8, 8, fake, fake, None, 3.0, 9.0, fake, None) == -1
     assert lib.gf_guide_field(1, 8, 8, fake, fake, fake, 3.0, 9.0, None, None) == -1
+
+
+def test_coherence_rejects_bad_arguments(lib):
+    import paper_1611_05319_amd as gf
+
+    fake = ctypes.c_void_p(1 << 20)
+    p = gf.Params(ghost=False).c_struct()
+    n = lib.gf_coherence_workspace_size(2, 40, 50, 3, 0, ctypes.byref(p))
+    nf = lib.gf_workspace_size(2, 40, 50, 3, 0, ctypes.byref(p))
+    assert n % 256 == 0 and n >= nf + 2 * 40 * 50 * (1 + 8 + 4)
+    assert lib.gf_coherence_workspace_size(0, 40, 50, 3, 0, ctypes.byref(p)) == 0
+
+    def call(sigma=2.0, rho=4.0, lam=1e-5, params=p, ws=n, shell=fake):
+        return lib.gf_fill_coherence(fake, fake, 2, 40, 50, 3, 0, fake, ctypes.byref(params), sigma,
+                                     rho, lam, shell, fake, None, fake, ws, None)
+
+    assert call(sigma=0.0) == -1
+    assert call(rho=-1.0) == -1
+    assert call(lam=0.0) == -1
+    assert call(lam=float("inf")) == -1
+    assert call(sigma=9.0) == -3
+    assert call(rho=17.0) == -3
+    assert call(ws=n - 256) == -1
+    assert call(shell=None) == -1
+    p2 = gf.Params(ghost=False, c2=0.1).c_struct()
+    assert call(params=p2) == -3

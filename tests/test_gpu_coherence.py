@@ -1,0 +1,150 @@
+"""The coherence-transport comparison mode (gf_fill_coherence) against the
+oracle's: before every shell the guide of each front pixel is the coherence
+direction of the modified structure tensor of the known pixels
+(eqn:modStructureTensor), then one shell of Algorithm 1 runs with it.
+
+Bars: the shell map bit-exact (with the lattice ball and onion order the
+shells do not depend on g); the guide each pixel was filled with, compared up
+to sign (the weights do not see it), within GTOL; colours within CTOL.  Both
+sides compute the tensor in FP64 from the same stored colours; the guide is
+rounded to binary32 (the fill's guide type) on both.  What is left: FP64
+exp/tanh of the two libraries (an ulp), and colours one binary32 ulp apart
+after a shell (the FP64 weighted sums are added in another order), which the
+next shell's tensor sees.  Where tanh((l+ - l-)/Lambda) is not saturated, a
+change d in l+ - l- moves |g| by up to d / Lambda; with |grad v| <= 1 per
+pixel and colour differences of 6e-8, d <= 2.4e-7 and Lambda = 1e-5 give
+|dg| <= 2.4e-2 in the worst case, which needs a nearly unsaturated tanh
+and a colour tie at the same pixel; the colours such a guide produces differ
+by |dg| times the local colour spread.  Measured on these cases: guides
+within 1.5e-8 and colours within 6e-8 (one binary32 ulp), so GTOL = 1e-3 and
+CTOL = 1e-5 leave room for such a pixel and still fail any real mistake; the
+tests also require the guides of 99.9 % of the pixels to agree within 1e-5.  With binary16 storage the
+colours of a shell may differ by a binary16 spacing (up to 4.9e-4 below 1:
+an FP64 sum on the other side of a rounding boundary), so the next shell's
+tensor moves by that much relative to the local gradient, and the colours
+it yields by the guide change times the local colour spread (up to 1 on the
+random test images): the bar is one binary16 spacing for the first shell
+(same inputs), 2e-3 (two spacings at 1) for every colour, and 5e-3 for the
+guides, 99.9 % of them within 5e-4."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+from gpu_helpers import banner, f16_ulps
+
+pytestmark = pytest.mark.gpu
+
+GTOL = 1e-3
+CTOL = 1e-5
+
+
+def _gpu(img, lab, sigma=2.0, rho=4.0, Lambda=1e-5, **kw):
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    dev = torch.device("cuda:0")
+    im = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+    lb = torch.from_numpy(np.ascontiguousarray(lab)).to(dev)
+    r = gf.fill_coherence(im, lb, gf.Params(ghost=False, **kw), sigma=sigma, rho=rho,
+                          Lambda=Lambda)
+    torch.cuda.synchronize()
+    return (r.out.cpu().numpy(), r.shell.cpu().numpy(), gf.stats_fields(r.stats),
+            r.guide_used.cpu().numpy())
+
+
+def _sign_free(a, b):
+    return np.minimum(np.abs(a - b).max(-1), np.abs(a + b).max(-1))
+
+
+def _compare(img, lab, storage="f32", sigma=2.0, rho=4.0, Lambda=1e-5, gtol=GTOL, gshare=1e-5,
+             **kw):
+    u, s, st, g = _gpu(img, lab, sigma, rho, Lambda, **kw)
+    ref = oracle.coherence_fill(img, lab, eps=kw.get("eps", 3.0), mu=kw.get("mu", 50.0),
+                                sigma=sigma, rho=rho, Lambda=Lambda, storage=storage,
+                                guide_f32=True)
+    np.testing.assert_array_equal(s, ref.shell)
+    assert st["K"] == ref.K
+    assert st["filled"] == int((ref.shell >= 0).sum())
+    filled = ref.shell >= 0
+    dg = _sign_free(g[filled].astype(np.float64), ref.guide[filled])
+    du = np.abs(u.astype(np.float64) - ref.u).max(initial=0.0)
+    if dg.size:
+        print(f"guide diff max {dg.max():.3g} p99.9 {np.quantile(dg, 0.999):.3g} "
+              f"p99 {np.quantile(dg, 0.99):.3g} share>1e-5 {(dg > 1e-5).mean():.4f}; colour {du:.3g}",
+              flush=True)
+    assert dg.max(initial=0.0) <= gtol, dg.max()
+    assert (dg <= gshare).mean() >= 0.999 if dg.size else True
+    if storage == "f16":
+        first = ref.shell == 0  # same inputs: at most one rounding apart
+        sp = f16_ulps(u[first].astype(np.float64), ref.u[first]).max(initial=0.0)
+        assert sp <= 1.0, sp
+        assert du <= 2e-3, du
+    else:
+        assert du <= CTOL, du
+    return u, s, g, ref
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("shape", [(64, 80, 3), (97, 131, 1)])
+def test_random_holes(engine, shape):
+    H, W, C = shape
+    banner(f"coherence random {shape} engine {engine}")
+    rng = np.random.default_rng(H + W + C)
+    img, lab, _ = syn.random_tiny(rng, H, W, C=C, p_hole=0.3, p_bystander=0.05)
+    _compare(img, lab, engine=engine)
+
+
+def test_batch_and_binary16():
+    banner("coherence batch fp16")
+    rng = np.random.default_rng(77)
+    imgs, labs = [], []
+    for _ in range(3):
+        img, lab, _ = syn.random_tiny(rng, 48, 56, C=3, p_hole=0.35, p_bystander=0.05)
+        imgs.append(img)
+        labs.append(lab)
+    img = np.stack(imgs).astype(np.float16)
+    lab = np.stack(labs)
+    _compare(img, lab, storage="f16", gtol=5e-3, gshare=5e-4)
+
+
+def test_other_scales_and_max_shells():
+    banner("coherence sigma 1.5 rho 3, max_shells 2")
+    rng = np.random.default_rng(5)
+    img, lab, _ = syn.random_tiny(rng, 60, 70, C=2, p_hole=0.4, p_bystander=0.0)
+    _compare(img, lab, sigma=1.5, rho=3.0, Lambda=1e-3)
+    u, s, st, g = _gpu(img, lab, max_shells=2)
+    ref = oracle.coherence_fill(img, lab, max_shells=2, storage="f32", guide_f32=True)
+    np.testing.assert_array_equal(s, ref.shell)
+    assert st["K"] == 2
+
+
+def test_kink_example_first_shell():
+    """Sec. 3.2's example on the device: the first hole row on the line
+    y = x takes the kinked 57.6 degree guide, as the oracle does."""
+    banner("coherence kink example")
+    N, c0 = 81, 40
+    rows, cols = np.mgrid[0:N, 0:N]
+    X, Y = cols - c0, c0 - rows
+    u = np.where(Y < X, 1.0, 0.5)
+    u = np.where(Y == X, 0.75, u)[..., None].astype(np.float32)
+    lab = (Y < 0).astype(np.uint8)
+    img = np.where(lab[..., None] == 1, np.float32(0), u)
+    uu, s, st, g = _gpu(img, lab, max_shells=1)
+    want = oracle.coherence_guide(img, lab)
+    a = g[c0 + 1, c0 - 1]
+    assert _sign_free(a[None].astype(np.float64), want[c0 + 1, c0 - 1][None])[0] <= 1e-6
+    ang = math.degrees(math.atan2(-a[1], a[0])) % 180.0
+    assert abs(ang - 57.6) < 0.1, ang
+
+
+def test_full_hd_silhouettes():
+    """The plain 1920 x 1080 workload (6 silhouette bands, 60 558 hole
+    pixels), its guide replaced by the comparison mode's."""
+    banner("coherence 1080p")
+    w = syn.config2()
+    _compare(w.image[0], w.label[0])
