@@ -178,6 +178,123 @@ def deep_front(w3, torch, gf, autotune, dev, args):
                          "algorithmic_bytes": nbytes, "event_ms_per_launch": round(ev, 5)}}
 
 
+def guidance_extras(w2, torch, gf, dev, args):
+    """The two guide constructions on the 1080p frame: the spline guide
+    field (Sec. 3.2) from six random Bezier splines sampled every 2 px, and
+    the coherence-transport comparison fill (guide re-estimated from the
+    modified structure tensor before every shell, lattice ball)."""
+    B, H, W, C = w2.image.shape
+    lab = torch.from_numpy(w2.label).to(dev)
+    rng = np.random.default_rng(12)
+    seg, off = syn.pack_segments([syn.spline_segments(rng, H, W, n_splines=6, spacing=2.0)])
+    seg_d = torch.from_numpy(seg).to(dev)
+    off_d = torch.from_numpy(off).to(dev)
+    g_out = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
+
+    def run_guide():
+        gf.guide_field(lab, seg_d, off_d, out=g_out, check_offsets=False)
+
+    n_hole = int((w2.label == 1).sum())
+    wall_g, ev_g = time_steps(run_guide, max(5, args.steps // 5), 2, torch)
+    img = torch.from_numpy(w2.image).to(dev)
+    out = torch.empty_like(img)
+    ws = gf.Workspace()
+    pc = gf.Params(eps=w2.eps, mu=w2.mu, ghost=False)
+    r = gf.fill_coherence(img, lab, pc, out=out, workspace=ws)
+    st = gf.stats_fields(r.stats)
+
+    def run_ct():
+        gf.fill_coherence(img, lab, pc, out=out, workspace=ws, want_guide=False)
+
+    wall_c, _ = time_steps(run_ct, max(3, args.steps // 10), 1, torch)
+    return {
+        "guide_field": {"workload": "1920x1080 silhouette holes, 6 random Bezier splines as "
+                                    f"{seg.shape[0]} segments, eta=3, cutoff 9 px",
+                        "ms": round(ev_g, 4), "hole_px": n_hole, "segments": int(seg.shape[0]),
+                        "gpairs_per_s": round(n_hole * seg.shape[0] / (ev_g * 1e-3) / 1e9, 2)},
+        "coherence": {"workload": "1920x1080 RGB binary32, 6 silhouette bands, guide from the "
+                                  "modified structure tensor (sigma=2, rho=4, Lambda=1e-5) before "
+                                  "every shell, lattice ball, eps=3, mu=50",
+                      "ms_per_fill": round(wall_c, 4), "shells": st["K"], "filled_px": st["filled"],
+                      "us_per_shell": round(wall_c * 1e3 / max(st["K"], 1), 2),
+                      "mpix_filled_per_s": round(st["filled"] / (wall_c * 1e-3) / 1e6, 2)},
+    }
+
+
+def studies(torch, gf, dev, args):
+    """The paper's synthetic studies on the device: signal degradation of the
+    73-degree band at its four resolutions (L^1 / L^2 error over the hole and
+    at the cross-sections y = 0.25 and 0, observed rates), and a camera-pan
+    video batch (16 frames 1920x1080 binary16, one launch)."""
+    res = []
+    for W in (200, 400, 4000, 8000):
+        prob = syn.degradation_problem(W)
+        i = torch.from_numpy(prob.image[None]).to(dev)
+        l = torch.from_numpy(prob.label[None]).to(dev)
+        g = torch.from_numpy(prob.guide[None]).to(dev)
+        plan = gf.FillPlan(i, l, g, gf.Params(eps=3.0, mu=50.0))
+        plan.run()
+        torch.cuda.synchronize()
+        st = gf.stats_fields(plan.stats)
+        wall, _ = time_steps(plan.run, 3, 1, torch)
+        u = plan.out[0, ..., 0].double().cpu().numpy()
+        e = np.abs(u - prob.exact)
+        hole = prob.label == 1
+        row = {"px": f"{W}x{W // 2}", "ms": round(wall, 3), "shells": st["K"],
+               "L1": float(prob.h * prob.h * e[hole].sum()),
+               "L2": float(np.sqrt(prob.h * prob.h * (e[hole] ** 2).sum()))}
+        for yc in (0.25, 0.0):
+            j = int(np.argmin(np.abs(prob.y - yc)))
+            sel = hole[j]
+            row[f"L1_y{yc}"] = float(prob.h * e[j, sel].sum())
+        res.append(row)
+        del i, l, g, plan
+    for p in ("L1", "L2"):
+        a, b = res[0], res[-1]
+        w0, w1 = 200, 8000
+        for r in res:
+            r[p] = round(r[p], 6)
+        res_rate = np.log(a[p] / b[p]) / np.log(w1 / w0)
+        res[-1][f"rate_{p}_200_to_8000"] = round(float(res_rate), 3)
+    wl, _ = syn.pan_video(seed=6, B=16, H=1080, W=1920, step=(3, 1))
+    i = torch.from_numpy(wl.image).to(dev)
+    l = torch.from_numpy(wl.label).to(dev)
+    g = torch.from_numpy(wl.guide).to(dev)
+    plan = gf.FillPlan(i, l, g, gf.Params(eps=wl.eps, mu=wl.mu, engine=gf.ENGINE_FRONT))
+    plan.run()
+    torch.cuda.synchronize()
+    st = gf.stats_fields(plan.stats)
+    wall, _ = time_steps(plan.run, 5, 1, torch)
+    return {"degradation": {"workload": "band |y - tan(73 deg) x| <= 0.1 on [-1,1]x[-0.5,0.5], "
+                                        "hole (-0.8,0.8)x(-0.3,0.3), eps=3, mu=50, guide along "
+                                        "the band", "resolutions": res},
+            "pan_video": {"workload": "16 x 1920x1080 RGB binary16 camera pan (3, 1) px per frame "
+                                      "over one scene, 6 silhouette bands, eps=3, mu=50, one launch",
+                          "hole_px": st["hole"], "shells": st["K"], "ms": round(wall, 4),
+                          "mpix_filled_per_s": round(st["filled"] / (wall * 1e-3) / 1e6, 2)}}
+
+
+def profile_coherence(args):
+    """Only the comparison fill of the 1080p frame (for rocprofv3)."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    w2 = syn.config2()
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(w2.image).to(dev)
+    lab = torch.from_numpy(w2.label).to(dev)
+    out = torch.empty_like(img)
+    ws = gf.Workspace()
+    pc = gf.Params(eps=w2.eps, mu=w2.mu, ghost=False)
+
+    def run_ct():
+        gf.fill_coherence(img, lab, pc, out=out, workspace=ws, want_guide=False)
+
+    wall, _ = time_steps(run_ct, args.steps, args.warmup, torch)
+    print(json.dumps({"profile": "coherence", "steps": args.steps, "ms_per_fill": wall}), flush=True)
+
+
 def profile_deep(args):
     """The 4K deep-front fill alone, one launch per step, autotuned launch."""
     w3 = syn.config3()
@@ -257,6 +374,8 @@ def main():
                     help="64-frame batch fill steps only (for rocprofv3)")
     ap.add_argument("--profile-grad", action="store_true",
                     help="16 x 512^2 forward + backward steps only (for rocprofv3)")
+    ap.add_argument("--profile-coherence", action="store_true",
+                    help="the coherence-transport comparison fill only (for rocprofv3)")
     ap.add_argument("--profile-deep", action="store_true",
                     help="3840x2160 deep-front fill steps only (for rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,6 +392,9 @@ def main():
         return
     if args.profile_grad:
         profile_grad(args)
+        return
+    if args.profile_coherence:
+        profile_coherence(args)
         return
     if args.profile_deep:
         profile_deep(args)
@@ -395,6 +517,8 @@ def main():
         del i4, l4, g4, plan_b, plans_1
         # deep front: 3840x2160, one 200-px band plus 20 discs, eps = 5, mu = 100
         out["deep_front"] = deep_front(w3, torch, gf, autotune, dev, args)
+        out.update(guidance_extras(w2, torch, gf, dev, args))
+        out["studies"] = studies(torch, gf, dev, args)
         # forward vs forward + backward (reverse-shell adjoint)
         i5 = torch.from_numpy(w5.image).to(dev)
         l5 = torch.from_numpy(w5.label).to(dev)

@@ -41,6 +41,8 @@ __all__ = [
     "silhouette_bands",
     "spline_guidance",
     "spline_segments",
+    "degradation_problem",
+    "pan_video",
     "pack_segments",
     "config1",
     "config2",
@@ -340,6 +342,66 @@ def pack_segments(frames) -> tuple[np.ndarray, np.ndarray]:
     off[1:] = np.cumsum([len(f) for f in frames])
     seg = np.concatenate(frames) if frames else np.zeros((0, 6), dtype=np.float32)
     return np.ascontiguousarray(seg, dtype=np.float32), off
+
+
+@dataclass
+class DegradationProblem:
+    """The signal-degradation study of Sec. 4: the band |y - tan(a) x| <= 0.1
+    on Omega = [-1, 1] x [-0.5, 0.5] with the hole D = (-0.8, 0.8) x
+    (-0.3, 0.3), rendered at W x W/2 pixels (h = 2 / W, pixel centres), the
+    guide along the band.  `exact` is the continuum solution sampled at the
+    pixel centres (the band carried straight across D); x, y the centres."""
+
+    image: np.ndarray   # H x W x 1 float32, 0 on the hole
+    label: np.ndarray   # H x W uint8
+    guide: np.ndarray   # H x W x 2 float32, (cos a, -sin a) on the hole
+    exact: np.ndarray   # H x W float64
+    x: np.ndarray       # W pixel-centre abscissae
+    y: np.ndarray       # H pixel-centre ordinates (row 0 at the top)
+    h: float
+
+
+def degradation_problem(W: int, angle_deg: float = 73.0, half_width: float = 0.1):
+    H = W // 2
+    h = 2.0 / W
+    x = -1.0 + (np.arange(W) + 0.5) * h
+    y = 0.5 - (np.arange(H) + 0.5) * h
+    X, Y = np.meshgrid(x, y)
+    t = math.tan(math.radians(angle_deg))
+    exact = (np.abs(Y - t * X) <= half_width).astype(np.float64)
+    hole = (np.abs(X) < 0.8) & (np.abs(Y) < 0.3)
+    img = np.where(hole, 0.0, exact)[..., None].astype(np.float32)
+    g = np.zeros((H, W, 2), dtype=np.float32)
+    g[..., 0] = np.float32(math.cos(math.radians(angle_deg)))
+    g[..., 1] = np.float32(-math.sin(math.radians(angle_deg)))  # rows grow downwards
+    g[~hole] = 0.0
+    return DegradationProblem(img, hole.astype(np.uint8), g, exact, x, y, h)
+
+
+def pan_video(seed: int = 6, B: int = 16, H: int = 1080, W: int = 1920, step=(3, 1),
+              margin: int = 8, dtype=np.float16):
+    """A camera pan over one static scene: frame t is the H x W window of a
+    larger canvas moved by t * step = (dx, dy) pixels; the canvas carries six
+    silhouette bands (the disocclusion holes of the full-HD recipe) and the
+    spline / structure-tensor guide.  Holes are kept at least `margin` pixels
+    from every frame border.  Returns (Workload of B frames, per-frame (x0, y0)
+    window origins in the canvas)."""
+    rng = np.random.default_rng(seed)
+    dx, dy = step
+    CW, CH = W + dx * (B - 1), H + dy * (B - 1)
+    img, label, guide = _frame_c2(rng, CH, CW)
+    origins = [(t * dx, t * dy) for t in range(B)]
+    # holes only where every frame sees them at least `margin` px inside
+    keep = np.zeros((CH, CW), dtype=bool)
+    keep[dy * (B - 1) + margin:H - margin, dx * (B - 1) + margin:W - margin] = True
+    label = np.where((label == 1) & ~keep, np.uint8(0), label)
+    guide = np.where((label == 1)[..., None], guide, np.float32(0)).astype(np.float32)
+    frames = [(img[y0:y0 + H, x0:x0 + W], label[y0:y0 + H, x0:x0 + W],
+               guide[y0:y0 + H, x0:x0 + W]) for x0, y0 in origins]
+    wl = Workload("pan", np.stack([f[0] for f in frames]).astype(dtype),
+                  np.stack([f[1] for f in frames]), np.stack([f[2] for f in frames]), 3.0, 50.0,
+                  {"seed": seed, "B": B, "H": H, "W": W, "step": list(step)})
+    return wl, origins
 
 
 def constant_guidance(H: int, W: int, angle_deg: float, label: np.ndarray) -> np.ndarray:

@@ -663,3 +663,42 @@ def test_coherence_fill_shells_are_the_lattice_onion_shells():
     ref = oracle.fill(img, lab, g, eps=3.0, mu=50.0, ghost=False)
     np.testing.assert_array_equal(r.shell, ref.shell)
     assert r.K == ref.K
+
+
+# ----------------------------------------------------------------------------
+# the signal-degradation study (Sec. 4)
+
+
+def _lp_over_hole(u, prob, p):
+    e = np.abs(u - prob.exact)[prob.label == 1]
+    return (prob.h * prob.h * (e ** p).sum()) ** (1.0 / p)
+
+
+def test_degradation_study_converges_at_the_theorem_rate():
+    """The band at 73 degrees carried across the hole at 200 x 100, 400 x 200
+    and 800 x 400: the error in L^p over the hole decreases at least like
+    h^(1/(2p)) (eqn:Lpbound, the rate for data with jumps), i.e. by a factor
+    >= 2^(1/(2p)) per halving of h; measured about 2^0.55 for p = 1 and
+    2^0.27 for p = 2."""
+    errs = {1: [], 2: []}
+    for W in (200, 400, 800):
+        prob = syn.degradation_problem(W)
+        r = oracle.fill(prob.image, prob.label, prob.guide, eps=3.0, mu=50.0)
+        assert r.n_unfilled == 0
+        for p in (1, 2):
+            errs[p].append(_lp_over_hole(r.u[..., 0], prob, p))
+    for p in (1, 2):
+        rates = [math.log2(a / b) for a, b in zip(errs[p], errs[p][1:])]
+        assert all(rt >= 0.9 / (2 * p) for rt in rates), (p, errs[p], rates)
+        assert all(rt <= 1.0 for rt in rates), (p, errs[p], rates)
+
+
+def test_rectangle_hole_shells_are_chessboard_distances():
+    """Onion order with the 8-neighbour active boundary peels a rectangular
+    hole in a fully known frame ring by ring: shell = chessboard distance to
+    the nearest known pixel, minus 1."""
+    prob = syn.degradation_problem(200)
+    r = oracle.fill(prob.image, prob.label, prob.guide, eps=3.0, mu=50.0)
+    d = ndimage.distance_transform_cdt(prob.label == 1, metric="chessboard")
+    np.testing.assert_array_equal(np.where(prob.label == 1, r.shell, -1),
+                                  np.where(prob.label == 1, d - 1, -1))
