@@ -6,6 +6,13 @@
 // spline holds the nearest segment (equal distances keep the first).  The
 // distances and the argmin are FP64 with no contraction, so the choice of
 // spline and the cutoff test are exact; the result is rounded to binary32.
+//
+// One workgroup per 32 x 32 tile.  A segment whose bounding box stays more
+// than the cutoff away from the tile's box cannot come within the cutoff of
+// any of its pixels; if it were nevertheless a pixel's nearest segment, the
+// pixel would get 0 either way.  So each tile keeps only the segments near it
+// (in their original order, which the tie rule needs), staged in LDS in
+// batches, and its hole pixels scan those.
 #pragma once
 
 #include "device_common.h"
@@ -17,72 +24,139 @@ struct GuideArgs {
     const float *seg;       // nseg x (x0, y0, x1, y1, gx, gy)
     const int32_t *seg_off; // B + 1
     float *guide;           // B x H x W x 2
-    long long HW, NP;
+    long long HW;
     int B, H, W;
+    int tiles_x, tiles_y;
     double eta, cutoff;
 };
 
-constexpr int kGuideChunk = 1024;  // pixels a workgroup scans per step
+constexpr int kGuideTile = 32;                          // tile edge (pixels)
+constexpr int kGuideSlots = kGuideTile * kGuideTile / kBlock;  // pixels per thread
+constexpr int kGuideBatch = 1024;                       // segments staged per batch
 
-// Each workgroup scans chunks of kGuideChunk pixels: pixels off the hole get
-// 0 at once, the hole pixels are listed in LDS (one atomic per wavefront) and
-// then taken densely, one per thread, over their frame's segments.
 __global__ __launch_bounds__(kBlock) void guide_kernel(GuideArgs A) {
-    __shared__ int s_list[kGuideChunk];
-    __shared__ int s_n;
+    __shared__ int s_pix[kGuideTile * kGuideTile];
+    __shared__ float s_seg[kGuideBatch * 6];
+    __shared__ int s_idx[kGuideBatch];
+    __shared__ int s_wave[kBlock / 64];
+    __shared__ int s_n, s_kept;
     const int tid = threadIdx.x;
-    const double den = 2.0 * A.eta * A.eta;
-    const double cut2 = A.cutoff * A.cutoff;
-    float2 *out = reinterpret_cast<float2 *>(A.guide);
-    const long long nchunk = (A.NP + kGuideChunk - 1) / kGuideChunk;
-    for (long long c = blockIdx.x; c < nchunk; c += gridDim.x) {
-        const long long p0 = c * kGuideChunk;
-        if (tid == 0) s_n = 0;
+    const int per_frame = A.tiles_x * A.tiles_y;
+    const int f = (int)blockIdx.x / per_frame;
+    const int t = (int)blockIdx.x - f * per_frame;
+    const int x0 = (t % A.tiles_x) * kGuideTile, y0 = (t / A.tiles_x) * kGuideTile;
+    const long long base = (long long)f * A.HW;
+    float2 *out = reinterpret_cast<float2 *>(A.guide) + base;
+    const uint8_t *lab = A.label + base;
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    // the tile's pixels: 0 off the hole, the hole pixels listed
+    for (int i = tid; i < kGuideTile * kGuideTile; i += kBlock) {  // uniform trip count
+        const int x = x0 + (i & (kGuideTile - 1)), y = y0 + i / kGuideTile;
+        const bool in = x < A.W && y < A.H;
+        const long long q = (long long)y * A.W + x;
+        const bool hole = in && lab[q] == 1;
+        if (in && !hole) out[q] = make_float2(0.0f, 0.0f);
+        const int slot = wave_append(hole, &s_n);
+        if (hole) s_pix[slot] = i;
+    }
+    __syncthreads();
+    const int n = s_n;
+    if (n == 0) return;
+
+    const double cut = A.cutoff;
+    const double cut2 = cut * cut;
+    // the tile's box of pixel centres, widened by the cutoff and a margin
+    // far above the rounding of the comparisons
+    const double bx0 = x0 - cut - 1e-3, by0 = y0 - cut - 1e-3;
+    const double bx1 = min(x0 + kGuideTile - 1, A.W - 1) + cut + 1e-3;
+    const double by1 = min(y0 + kGuideTile - 1, A.H - 1) + cut + 1e-3;
+    double best[kGuideSlots];
+    int arg[kGuideSlots];
+#pragma unroll
+    for (int e = 0; e < kGuideSlots; ++e) {
+        best[e] = INFINITY;
+        arg[e] = -1;
+    }
+    const int s0 = A.seg_off[f], s1 = A.seg_off[f + 1];
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int b0 = s0; b0 < s1; b0 += kGuideBatch) {
+        const int b1 = min(b0 + kGuideBatch, s1);
+        if (tid == 0) s_kept = 0;
         __syncthreads();
-        for (int i = tid; i < kGuideChunk; i += kBlock) {  // uniform trip count
-            const long long p = p0 + i;
-            const bool hole = p < A.NP && A.label[p] == 1;
-            if (p < A.NP && !hole) out[p] = make_float2(0.0f, 0.0f);
-            const int slot = wave_append(hole, &s_n);
-            if (hole) s_list[slot] = i;
-        }
-        __syncthreads();
-        const int n = s_n;
-        for (int e = tid; e < n; e += kBlock) {
-            const long long p = p0 + s_list[e];
-            const long long f = p / A.HW;
-            const int q = (int)(p - f * A.HW);
-            const int j = q / A.W, i = q - j * A.W;
-            const int s0 = A.seg_off[f], s1 = A.seg_off[f + 1];
-            double best = INFINITY;
-            int arg = -1;
-            for (int k = s0; k < s1; ++k) {
+        // keep the segments near the tile, in order: per round of kBlock
+        // segments, ballots give each kept one its rank
+        for (int r0 = b0; r0 < b1; r0 += kBlock) {
+            const int k = r0 + tid;
+            bool keep = false;
+            if (k < b1) {
                 const float *S = A.seg + 6ll * k;
-                const double x0 = S[0], y0 = S[1];
-                const double dx = (double)S[2] - x0, dy = (double)S[3] - y0;
-                const double qx = (double)i - x0, qy = (double)j - y0;
-                const double len2 = dx * dx + dy * dy;
-                double t = 0.0;
-                if (len2 > 0.0) {
-                    t = (qx * dx + qy * dy) / len2;
-                    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-                }
-                const double ex = qx - t * dx, ey = qy - t * dy;
-                const double d2 = ex * ex + ey * ey;
-                if (d2 < best) {
-                    best = d2;
-                    arg = k;
-                }
+                const double sx0 = fmin((double)S[0], (double)S[2]), sx1 = fmax((double)S[0], (double)S[2]);
+                const double sy0 = fmin((double)S[1], (double)S[3]), sy1 = fmax((double)S[1], (double)S[3]);
+                keep = sx1 >= bx0 && sx0 <= bx1 && sy1 >= by0 && sy0 <= by1;
             }
-            float2 g = make_float2(0.0f, 0.0f);
-            if (arg >= 0 && !(best > cut2)) {
-                const double fct = exp(-best / den);
-                g.x = (float)((double)A.seg[6ll * arg + 4] * fct);
-                g.y = (float)((double)A.seg[6ll * arg + 5] * fct);
+            const unsigned long long m = __ballot(keep);
+            if (lane == 0) s_wave[wave] = (int)__popcll(m);
+            __syncthreads();
+            int pos = s_kept;
+            for (int w = 0; w < wave; ++w) pos += s_wave[w];
+            pos += (int)__popcll(m & ((1ull << lane) - 1ull));
+            if (keep) {
+                const float *S = A.seg + 6ll * k;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) s_seg[pos * 6 + c] = S[c];
+                s_idx[pos] = k;
             }
-            out[p] = g;
+            __syncthreads();
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < kBlock / 64; ++w) tot += s_wave[w];
+                s_kept += tot;
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        const int nk = s_kept;
+#pragma unroll
+        for (int e = 0; e < kGuideSlots; ++e) {
+            const int pi = tid + e * kBlock;
+            if (pi >= n) continue;
+            const int i = s_pix[pi];
+            const double px = (double)(x0 + (i & (kGuideTile - 1))), py = (double)(y0 + i / kGuideTile);
+            for (int j = 0; j < nk; ++j) {
+                const float *S = s_seg + 6 * j;
+                const double sx = S[0], sy = S[1];
+                const double dx = (double)S[2] - sx, dy = (double)S[3] - sy;
+                const double qx = px - sx, qy = py - sy;
+                const double len2 = dx * dx + dy * dy;
+                double tt = 0.0;
+                if (len2 > 0.0) {
+                    tt = (qx * dx + qy * dy) / len2;
+                    tt = tt < 0.0 ? 0.0 : (tt > 1.0 ? 1.0 : tt);
+                }
+                const double ex = qx - tt * dx, ey = qy - tt * dy;
+                const double d2 = ex * ex + ey * ey;
+                if (d2 < best[e]) {
+                    best[e] = d2;
+                    arg[e] = s_idx[j];
+                }
+            }
+        }
+        __syncthreads();  // the next batch overwrites the staged segments
+    }
+    const double den = 2.0 * A.eta * A.eta;
+#pragma unroll
+    for (int e = 0; e < kGuideSlots; ++e) {
+        const int pi = tid + e * kBlock;
+        if (pi >= n) continue;
+        const int i = s_pix[pi];
+        const long long q = (long long)(y0 + i / kGuideTile) * A.W + x0 + (i & (kGuideTile - 1));
+        float2 g = make_float2(0.0f, 0.0f);
+        if (arg[e] >= 0 && !(best[e] > cut2)) {
+            const double fct = exp(-best[e] / den);
+            g.x = (float)((double)A.seg[6ll * arg[e] + 4] * fct);
+            g.y = (float)((double)A.seg[6ll * arg[e] + 5] * fct);
+        }
+        out[q] = g;
     }
 }
 

@@ -448,29 +448,25 @@ gf_status gf_guide_field(int B, int H, int W, const uint8_t *label, const float 
                          void *stream) {
     if (B < 1 || H < 1 || W < 1 || !label || !seg_off || !guide) return GF_EINVAL;
     if (!(eta > 0.0) || !(cutoff >= 0.0) || !isfinite(eta) || !isfinite(cutoff)) return GF_EINVAL;
-    if ((long long)B * H * W >= (1ll << 40)) return GF_EUNSUPPORTED;
     GuideArgs A;
     A.label = label;
     A.seg = seg;
     A.seg_off = seg_off;
     A.guide = guide;
     A.HW = (long long)H * W;
-    A.NP = (long long)B * H * W;
     A.B = B;
     A.H = H;
     A.W = W;
+    A.tiles_x = (W + kGuideTile - 1) / kGuideTile;
+    A.tiles_y = (H + kGuideTile - 1) / kGuideTile;
     A.eta = eta;
     A.cutoff = cutoff;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) { set_err("hipGetDevice", e); return GF_EDEVICE; }
-    const int cus = device_info(dev).cus;
-    const long long nchunk = (A.NP + kGuideChunk - 1) / kGuideChunk;
-    long long grid = (long long)(cus > 0 ? cus : 256) * 8;
-    if (grid > nchunk) grid = nchunk;
+    const long long grid = (long long)B * A.tiles_x * A.tiles_y;
+    if (grid >= (1ll << 31)) return GF_EUNSUPPORTED;
     void *kargs[] = {&A};
-    e = hipLaunchKernel(reinterpret_cast<const void *>(guide_kernel), dim3((unsigned)grid), dim3(kBlock),
-                        kargs, 0, reinterpret_cast<hipStream_t>(stream));
+    const hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(guide_kernel),
+                                         dim3((unsigned)grid), dim3(kBlock), kargs, 0,
+                                         reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
     return GF_OK;
 }

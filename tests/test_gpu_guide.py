@@ -86,3 +86,25 @@ def test_full_frame_from_random_beziers():
     assert seg.shape[0] > 1000
     got, ref = _compare(label[None], seg, off)
     assert (np.abs(got) > 0).any()
+
+
+def test_many_segments_per_tile_and_duplicates():
+    """More segments than one staging batch near every tile, and exact
+    duplicates (later copies with other directions): the first copy wins."""
+    rng = np.random.default_rng(44)
+    H, W = 70, 90
+    label = (rng.uniform(size=(2, H, W)) < 0.6).astype(np.uint8)
+    frames = []
+    for b in range(2):
+        n = 2600
+        a = rng.uniform(0, [W, H], size=(n, 2))
+        c = a + rng.normal(0, 2.0, size=(n, 2))
+        g = rng.normal(size=(n, 2))
+        g /= np.linalg.norm(g, axis=1, keepdims=True)
+        seg = np.concatenate([a, c, g], axis=1)
+        dup = seg[:300].copy()
+        dup[:, 4:] = -dup[:, 4:]
+        frames.append(np.concatenate([seg, dup]))
+    seg, off = synthetic.pack_segments(frames)
+    _compare(label, seg, off, 3.0, None)
+    _compare(label, seg, off, 2.0, 1.5)
