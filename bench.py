@@ -274,6 +274,30 @@ def studies(torch, gf, dev, args):
                           "mpix_filled_per_s": round(st["filled"] / (wall * 1e-3) / 1e6, 2)}}
 
 
+def profile_guide(args):
+    """Only the spline guide field of the 1080p frame (for rocprofv3)."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    w2 = syn.config2()
+    dev = torch.device("cuda:0")
+    B, H, W, C = w2.image.shape
+    lab = torch.from_numpy(w2.label).to(dev)
+    rng = np.random.default_rng(12)
+    seg, off = syn.pack_segments([syn.spline_segments(rng, H, W, n_splines=6, spacing=2.0)])
+    seg_d = torch.from_numpy(seg).to(dev)
+    off_d = torch.from_numpy(off).to(dev)
+    g_out = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
+
+    def run_guide():
+        gf.guide_field(lab, seg_d, off_d, out=g_out, check_offsets=False)
+
+    wall, ev = time_steps(run_guide, args.steps, args.warmup, torch)
+    print(json.dumps({"profile": "guide", "steps": args.steps, "event_ms": ev,
+                      "segments": int(seg.shape[0])}), flush=True)
+
+
 def profile_coherence(args):
     """Only the comparison fill of the 1080p frame (for rocprofv3)."""
     import torch
@@ -374,6 +398,8 @@ def main():
                     help="64-frame batch fill steps only (for rocprofv3)")
     ap.add_argument("--profile-grad", action="store_true",
                     help="16 x 512^2 forward + backward steps only (for rocprofv3)")
+    ap.add_argument("--profile-guide", action="store_true",
+                    help="the spline guide field only (for rocprofv3)")
     ap.add_argument("--profile-coherence", action="store_true",
                     help="the coherence-transport comparison fill only (for rocprofv3)")
     ap.add_argument("--profile-deep", action="store_true",
@@ -392,6 +418,9 @@ def main():
         return
     if args.profile_grad:
         profile_grad(args)
+        return
+    if args.profile_guide:
+        profile_guide(args)
         return
     if args.profile_coherence:
         profile_coherence(args)
