@@ -266,10 +266,16 @@ __device__ inline bool readable(int32_t s, int k) { return (unsigned)(s + 1) <= 
 // workgroup may still add to them), so the host deals out kLaunchSlots sets in
 // a ring and each launch clears the next launch's set.
 
+// The XCD this workgroup runs on: the hardware XCC id (bits 3:0 of the
+// XCC_ID register); workgroups on one XCD share its L2.
+__device__ __attribute__((always_inline)) inline int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcd - 1));
+}
+
 struct GridInfo {
     int lw;  // logical index of this workgroup among those taking part
     int n;   // workgroups taking part
-    int x;   // XCD group: blockIdx.x % kXcd
+    int x;   // XCD group: the XCD the workgroup runs on (hardware XCC id)
 };
 // what the barriers need, kept in LDS rather than registers: workgroups
 // taking part in this workgroup's group, groups with at least one
@@ -294,7 +300,7 @@ __device__ __attribute__((always_inline)) bool launch_start(int32_t *ctl, const 
     __shared__ int s_ok;    // 0 after a (never expected) start-up timeout
     __shared__ int s_nx[kXcd];
     const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
-    const int x = (int)(blockIdx.x % kXcd);
+    const int x = xcc_id();
     const int slot = ls.slot, next = (ls.slot + 1) % kLaunchSlots;
     if (tid == 0) {
         unsigned *tk = reinterpret_cast<unsigned *>(&ctl[xw(x, XF_TICKET + slot)]);
@@ -387,14 +393,17 @@ __device__ __attribute__((always_inline)) bool launch_start(int32_t *ctl, const 
 // ---------------------------------------------------------------------------
 // grid barrier over the workgroups taking part.  Arrivals are counted per XCD
 // group first, then per group, so no counter sees more than
-// max(n / 8, 8) serialised atomics.  Waves of a workgroup share the
-// CU's path to L2, so a workgroup-scope release plus one agent-scope release
-// (L2 write-back) by thread 0 publishes the workgroup's stores; waiting is a
-// relaxed spin (an acquire load would invalidate the caches on every
-// iteration) followed by one acquire.
+// max(n / 8, 8) serialised atomics.  A group is the set of workgroups on one
+// XCD, which share that XCD's L2: every wave first waits until its own
+// stores and atomics are acknowledged (they are then in the L2), so when the
+// group's last workgroup arrives, one agent-scope release by it (an L2
+// write-back) publishes the stores of the whole group, instead of one
+// write-back per workgroup.  Waiting is a relaxed spin (an acquire load would
+// invalidate the caches on every iteration) followed by one acquire.
 
 __device__ __attribute__((always_inline)) void grid_sync(int32_t *ctl, const GridInfo &gi) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are in the L2
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned x = (unsigned)gi.x;
@@ -404,10 +413,12 @@ __device__ __attribute__((always_inline)) void grid_sync(int32_t *ctl, const Gri
         unsigned *top = (unsigned *)&ctl[G_TOP];
         unsigned *grp = (unsigned *)&ctl[xw((int)x, XF_BAR)];
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // also orders the load above
+        __builtin_amdgcn_s_waitcnt(0);  // the load completes before the arrival
         const unsigned a = __hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         bool last = false;
         if (a == per_group - 1) {
+            // every workgroup of the group has its stores in this L2: write it back
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             // the reset must be published before the group arrives at the top
             __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
@@ -449,6 +460,7 @@ __device__ __attribute__((always_inline)) SyncSum grid_sync_sum(int32_t *ctl, co
     typedef unsigned long long u64;
     constexpr u64 kLow48 = (1ull << 48) - 1ull;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are in the L2
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned x = (unsigned)gi.x;
@@ -458,12 +470,14 @@ __device__ __attribute__((always_inline)) SyncSum grid_sync_sum(int32_t *ctl, co
         u64 *top = reinterpret_cast<u64 *>(&ctl[G_TOP2]);
         u64 *grp = reinterpret_cast<u64 *>(&ctl[xw((int)x, XF_SUM)]);
         const u64 g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 48;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);  // the load completes before the arrival
         const u64 add = (1ull << 48) | ((u64)(flag ? 1u : 0u) << 32) | (u64)a;
         const u64 prior = __hip_atomic_fetch_add(grp, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         u64 word = 0;
         bool have = false;
         if ((prior >> 48) == per_group - 1) {
+            // every workgroup of the group has its stores in this L2: write it back
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const u64 gsum = (prior + add) & kLow48;
             __hip_atomic_store(grp, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
