@@ -131,6 +131,14 @@ template <> __device__ inline void store_colours<__half>(__half *dst, const floa
 // the readable sets do not depend on the timing.
 // NU > 1: each lane's first NU window pixels are loaded with every load in
 // flight at once (more registers), the rest one after another.
+// Window pixels a lane of the fill loads before it stores any to LDS: more
+// loads in flight per round trip against more registers held.  Measured on
+// the 1080p, 4K, 64-frame and 16-frame workloads: 7 where registers allow,
+// 2 for the binary16 kernel with 8 lanes, which is at its register limit.
+template <typename TS, int G> __host__ __device__ constexpr int stage_unroll() {
+    return sizeof(TS) == 2 && G == 8 ? 2 : 7;
+}
+
 template <typename TS, int G, int NU = 1>
 __device__ inline void stage_window(const int32_t *S, const TS *U, int W, int H, int C, int X, int Y,
                                     int D, int32_t *st, TS *col, int l) {
@@ -243,6 +251,9 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
     const int W = A.W, H = A.H;
     const bool track = A.tracking != 0;
     GF_T0();
+    GF_RT_DECL(rt_stage);
+    GF_RT_DECL(rt_fill);
+    GF_RT_DECL(rt_emit);
 
     // ---- init: copy, shell codes, hole count, shell-0 front ----------------
     {
@@ -447,10 +458,15 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                         const long long f = gidx / A.HW;
                         const int p = (int)(gidx - f * A.HW);
                         const int y = p / W, x = p - y * W;
-                        stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
+                        GF_RT_BEGIN(rt_stage);
+                        stage_window<TS, G, stage_unroll<TS, G>()>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
                                             W, H, A.C, x, y, D, w_st, w_col, l);
+                        GF_RT_END(rt_stage);
+                        GF_RT_BEGIN(rt_fill);
                         const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item],
                                                                  k, l, D, w_st, w_col);
+                        GF_RT_END(rt_fill);
+                        GF_RT_BEGIN(rt_emit);
                         if (ok) {
                             if (l < 8) {  // emit the unfilled 8-neighbours (dedup by CAS on the map)
                                 const int d = l < 4 ? l : l + 1;
@@ -469,6 +485,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                         } else if (l == 0) {
                             stage_push(lst, (int)gidx, nxt_list, nxt_cnt);  // not ready: carry over
                         }
+                        GF_RT_END(rt_emit);
                     }
                 }
             }
@@ -511,7 +528,7 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
                         const long long f = px / A.HW;
                         const int q = (int)(px - f * A.HW);
                         const int y = q / W, x = q - y * W;
-                        stage_window<TS, G>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
+                        stage_window<TS, G, stage_unroll<TS, G>()>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.out) + f * A.HW * A.C,
                                             W, H, A.C, x, y, D, w_st, w_col, l);
                         const bool ok = global_fill_pixel<TS, G>(A, s_off, s_rinv, T, px, gv, k, l, D,
                                                                  w_st, w_col);
@@ -566,6 +583,9 @@ __global__ __launch_bounds__(kBlock, G == 16 ? 2 : 3) void fill_kernel(FillArgs 
     }
 
     // ---- finish -------------------------------------------------------------
+    GF_RT_FLUSH(11, rt_stage);
+    GF_RT_FLUSH(12, rt_fill);
+    GF_RT_FLUSH(13, rt_emit);
     if (track) total_filled = ld_ctl(ctl, G_FILLED);
     if (total_filled < total_hole) {  // leftovers never became ready
         const long long lo = A.NP * lw / nblk, hi = A.NP * (lw + 1) / nblk;
