@@ -77,7 +77,7 @@ def launch_key(p, H, W, C):
     if p.engine == gf.ENGINE_TILED:
         tw, th, S, _, _, G = gf.tile_geometry(H, W, C, params=p)
         return (f"engine=0 tile={tw}x{th} pass_shells={S} group={G} "
-                f"tile_threads={p.tile_threads or 1024} blocks_per_cu={p.blocks_per_cu}")
+                f"tile_threads={p.tile_threads or 768} blocks_per_cu={p.blocks_per_cu}")
     return f"engine=1 group={p.group} blocks_per_cu={p.blocks_per_cu}"
 
 

@@ -83,7 +83,7 @@ typedef struct {
     int32_t tile_w, tile_h; /* tiled engine: tile interior in pixels, 0 = auto (<= 256) */
     int32_t pass_shells;    /* tiled engine: shells per grid sync, 0 = auto (<= 32); the halo
                                pass_shells * ceil(eps) may not exceed tile_w or tile_h */
-    int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (auto), 256, 512, 768, 1024;
+    int32_t tile_threads;   /* tiled engine: threads per workgroup, 0 (768), 256, 512, 768, 1024;
                                must be 0 with GF_ENGINE_FRONT */
     double c2;              /* < 0: no data term; >= 0: the data term of eqn:ready2 (Sec. 3.4),
                                ready also requires |g(x)| > c2, until the first shell in which

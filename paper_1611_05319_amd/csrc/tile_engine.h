@@ -48,6 +48,7 @@ struct TileArgs {
 
 
 constexpr int kWinPerThread = 4;     // window pixels staged per thread per round trip
+constexpr int kStagePerThread = 2;   // the same in the one-round staging (fewer threads)
 constexpr int kMaxWindow = 8192;     // window pixels (uint16 local lists)
 constexpr int kTileStageCap = 512;   // LDS staging of next-pass tiles per workgroup
 constexpr int kTileStaticLds = 8192; // bytes of static LDS the tile kernel may use
@@ -358,42 +359,88 @@ __global__ __launch_bounds__(NT) void tile_kernel(TileArgs A) {
                     nbh = A.t_hole[f * tpf + ny * A.tiles_x + nx];
             }
             const float2 *Gd = reinterpret_cast<const float2 *>(A.guide) + (long long)f * A.HW;
-            // 1. stage the window in two round trips: states (readable before the
-            //    pass / bystander / hole; pixels filled by neighbours during this pass
-            //    count as hole), then colours of readable pixels (from the input for
-            //    pixels known from the start, else from the output) and guides of
-            //    hole pixels
-            for (int base = 0; base < WN; base += kWinPerThread * NT) {
-                int32_t code[kWinPerThread];
+            // 1. stage the window.  With 1024 threads (128 registers a lane): in
+            //    two round trips, the states (readable before the pass / bystander /
+            //    hole; pixels filled by neighbours during this pass count as hole),
+            //    then colours of readable pixels (from the input for pixels known
+            //    from the start, else from the output) and guides of hole pixels.
+            //    With fewer threads there are registers for one round trip: state,
+            //    guide, input colour and (after the first pass) output colour of
+            //    a pixel are loaded together and the state then picks.
+            if constexpr (NT >= 1024) {
+                for (int base = 0; base < WN; base += kWinPerThread * NT) {
+                    int32_t code[kWinPerThread];
 #pragma unroll
-                for (int r = 0; r < kWinPerThread; ++r) {
-                    const int i = base + tid + r * NT;
-                    code[r] = S_BYSTANDER;
-                    if (i < WN) {
-                        const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
-                        const int x = ox0 + wx, y = oy0 + wy;
-                        if (x >= 0 && x < W && y >= 0 && y < H) {
-                            const int32_t s = S[y * W + x];
-                            code[r] = s == -1                    ? kKnown
-                                      : (s >= 0 && s < k0)         ? S_READABLE
-                                      : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
+                    for (int r = 0; r < kWinPerThread; ++r) {
+                        const int i = base + tid + r * NT;
+                        code[r] = S_BYSTANDER;
+                        if (i < WN) {
+                            const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
+                            const int x = ox0 + wx, y = oy0 + wy;
+                            if (x >= 0 && x < W && y >= 0 && y < H) {
+                                const int32_t s = S[y * W + x];
+                                code[r] = s == -1                    ? kKnown
+                                          : (s >= 0 && s < k0)         ? S_READABLE
+                                          : (s == S_BYSTANDER || s == S_UNFILLED) ? S_BYSTANDER : S_HOLE;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kWinPerThread; ++r) {
+                        const int i = base + tid + r * NT;
+                        if (i < WN) {
+                            const bool known = code[r] == kKnown;
+                            st[i] = known ? S_READABLE : code[r];
+                            const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
+                            const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
+                            if (known || code[r] == S_READABLE) {
+                                const TS *src = known ? Ui : U;
+#pragma unroll
+                                for (int ch = 0; ch < 4; ++ch) col[i * CP + ch] = ch < C ? src[q * C + ch] : TS(0.0f);
+                            } else if (code[r] == S_HOLE) {
+                                gd[i] = Gd[q];
+                            }
                         }
                     }
                 }
+            } else {
+                for (int base = 0; base < WN; base += kStagePerThread * NT) {
+                    int32_t sv[kStagePerThread];
+                    TS ci[kStagePerThread][4], co[kStagePerThread][4];
+                    float2 gv[kStagePerThread];
 #pragma unroll
-                for (int r = 0; r < kWinPerThread; ++r) {
-                    const int i = base + tid + r * NT;
-                    if (i < WN) {
-                        const bool known = code[r] == kKnown;
-                        st[i] = known ? S_READABLE : code[r];
-                        const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
-                        const long long q = (long long)(oy0 + wy) * W + (ox0 + wx);
-                        if (known || code[r] == S_READABLE) {
-                            const TS *src = known ? Ui : U;
+                    for (int r = 0; r < kStagePerThread; ++r) {
+                        const int i = base + tid + r * NT;
+                        sv[r] = S_BYSTANDER;
+                        if (i < WN) {
+                            const int wy = div_small(i, WW, rWW), wx = i - wy * WW;
+                            const int x = ox0 + wx, y = oy0 + wy;
+                            if (x >= 0 && x < W && y >= 0 && y < H) {
+                                const long long q = (long long)y * W + x;
+                                sv[r] = S[q];
+                                gv[r] = Gd[q];
 #pragma unroll
-                            for (int ch = 0; ch < 4; ++ch) col[i * CP + ch] = ch < C ? src[q * C + ch] : TS(0.0f);
-                        } else if (code[r] == S_HOLE) {
-                            gd[i] = Gd[q];
+                                for (int ch = 0; ch < 4; ++ch) {
+                                    ci[r][ch] = ch < C ? Ui[q * C + ch] : TS(0.0f);
+                                    co[r][ch] = ch < C && k0 > 0 ? U[q * C + ch] : TS(0.0f);
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < kStagePerThread; ++r) {
+                        const int i = base + tid + r * NT;
+                        if (i < WN) {
+                            const int32_t sp = sv[r];
+                            const bool known = sp == -1, earlier = sp >= 0 && sp < k0;
+                            const bool bys = sp == S_BYSTANDER || sp == S_UNFILLED;
+                            st[i] = known || earlier ? S_READABLE : (bys ? S_BYSTANDER : S_HOLE);
+                            if (known || earlier) {
+#pragma unroll
+                                for (int ch = 0; ch < 4; ++ch) col[i * CP + ch] = known ? ci[r][ch] : co[r][ch];
+                            } else if (!bys) {
+                                gd[i] = gv[r];
+                            }
                         }
                     }
                 }

@@ -27,9 +27,11 @@ def _device():
     gf.load()
 
 
-# launch variants: the tiled engine (1024- and 256-thread workgroups) and the
-# global-front engine
-LAUNCH = {"tiled": {}, "tiled256": {"tile_threads": 256}, "front": {"engine": 1}}
+# launch variants: the tiled engine (default 768-thread, 1024- and 256-thread
+# workgroups; the 1024-thread form stages its windows in two round trips, the
+# others in one) and the global-front engine
+LAUNCH = {"tiled": {}, "tiled1024": {"tile_threads": 1024}, "tiled256": {"tile_threads": 256},
+          "front": {"engine": 1}}
 ENGINES = list(LAUNCH)
 
 
@@ -167,6 +169,7 @@ FORMS = [
     {"tile_threads": 256}, {"tile_threads": 512}, {"tile_threads": 512, "pass_shells": 2},
     {"group": 4}, {"group": 4, "tile_threads": 512}, {"group": 4, "tracking": False},
     {"tile_threads": 768}, {"tile_threads": 768, "group": 16, "pass_shells": 3},
+    {"tile_threads": 1024}, {"tile_threads": 1024, "group": 16, "pass_shells": 3},
     {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "pass_shells": 4},
     {"tile_threads": 256, "tile_w": 24, "tile_h": 12, "pass_shells": 2, "tracking": False},
     {"tile_threads": 256, "tile_w": 16, "tile_h": 16, "group": 16},
