@@ -148,3 +148,31 @@ def test_full_hd_silhouettes():
     banner("coherence 1080p")
     w = syn.config2()
     _compare(w.image[0], w.label[0])
+
+
+def test_in_place_and_enclosed_holes():
+    """The output may alias the input; a hole walled in by bystanders never
+    fills (shell -3, input colour kept), as in the oracle."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner("coherence in place, enclosed hole")
+    rng = np.random.default_rng(21)
+    img, lab, _ = syn.random_tiny(rng, 40, 48, C=3, p_hole=0.3, p_bystander=0.0)
+    lab[5:15, 5:15] = 2
+    lab[7:13, 7:13] = 1  # enclosed by bystanders
+    ref = oracle.coherence_fill(img, lab, storage="f32", guide_f32=True)
+    dev = torch.device("cuda:0")
+    im = torch.from_numpy(np.ascontiguousarray(img)).to(dev)
+    lb = torch.from_numpy(np.ascontiguousarray(lab)).to(dev)
+    r = gf.fill_coherence(im, lb, gf.Params(ghost=False), out=im)
+    torch.cuda.synchronize()
+    s = r.shell.cpu().numpy()
+    np.testing.assert_array_equal(s, ref.shell)
+    assert (s[7:13, 7:13] == -3).all()
+    st = gf.stats_fields(r.stats)
+    assert st["unfilled"] == 36 and st["hole"] == int((lab == 1).sum())
+    u = im.cpu().numpy().astype(np.float64)
+    assert np.abs(u - ref.u).max() <= CTOL
+    np.testing.assert_array_equal(u[7:13, 7:13], img[7:13, 7:13])
