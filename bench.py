@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=512, help="plain copy size in --profile mode")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (frames shard with no exchange; "
+        print("bench.py: the benchmark runs on one GPU only (frames shard with no exchange; "
               "see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

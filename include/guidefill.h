@@ -59,7 +59,7 @@ typedef enum {
     GF_OK = 0,
     GF_EINVAL = -1,     /* bad argument (null pointer, size, parameter, workspace too small) */
     GF_EDEVICE = -2,    /* a HIP call failed (launch, occupancy query, ...) */
-    GF_EUNSUPPORTED = -3 /* valid request outside what this build supports */
+    GF_EUNSUPPORTED = -3 /* valid request outside what the library supports */
 } gf_status;
 
 typedef enum { GF_F32 = 0, GF_F16 = 1 } gf_dtype;
@@ -174,7 +174,7 @@ gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dty
                   void *stream);
 
 /*
- * Reverse-mode derivative of a completed fill (this build's extension; the
+ * Reverse-mode derivative of a completed fill (an extension beyond the paper; the
  * fill is linear in the known colours, Algorithm 1).  One persistent launch:
  * the filled pixels are grouped by shell from the shell map (a counting sort
  * inside the launch), then the shells are replayed from the last to the

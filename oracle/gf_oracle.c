@@ -406,7 +406,7 @@ int gfo_fill(int B, int H, int W, int C, const double *img_in, const uint8_t *la
 }
 
 /*
- * Reverse-mode derivative of the fill (this build's extension: the fill is
+ * Reverse-mode derivative of the fill (an extension beyond the paper: the fill is
  * linear in the known colours with coefficients fixed by labels and guide,
  * Algorithm 1).  Given dL/du_out, returns dL/du_in and dL/dg, with the
  * readable sets and ready decisions held fixed (they are piecewise constant in
