@@ -13,8 +13,10 @@
 // One workgroup per 16 x 16 (or 8 x 8) tile: tiles without a front pixel leave
 // at once; the others stage colours and known flags of the tile plus a halo of
 // floor(2 rho) + 1 + floor(2 sigma) pixels in LDS and compute v, T and J there
-// in FP64, in the order the definitions sum (rows outer, columns inner), so no
-// intermediate leaves the CU.
+// in FP64, so no intermediate leaves the CU.  The Gaussian weight of v is the
+// product of its row and column factors, so v is summed in two passes (rows,
+// then columns: 2 (2 floor(2 sigma) + 1) terms a pixel instead of its square);
+// J keeps the direct sum, over the front pixels only.
 #pragma once
 
 #include "device_common.h"
@@ -33,10 +35,12 @@ struct CtArgs {
 };
 
 // LDS regions of one tile: T over the tile plus rr, v one pixel wider, the
-// colours another rs wider.  Doubles first, then floats, then bytes.
+// colours another rs wider; the row sums of the smoothing over the colour
+// region's rows and v's columns.  Regions whose lifetimes do not overlap
+// share memory: the row sums, later T; the colours, later v.
 struct CtLds {
     int RU, RV, RT;
-    size_t v, T, ws, wr, u, kn, vok, total;
+    size_t rsum, T, u, v, w1, wr, kn, vok, total;
 };
 
 __host__ __device__ inline size_t ct_align16(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -46,12 +50,15 @@ __host__ __device__ inline CtLds ct_lds(int tile, int rs, int rr, int C) {
     L.RT = tile + 2 * rr;
     L.RV = L.RT + 2;
     L.RU = L.RV + 2 * rs;
+    const size_t rsum = (size_t)L.RU * L.RV * (C + 1) * sizeof(double);
+    const size_t tens = (size_t)L.RT * L.RT * 3 * sizeof(double);
+    const size_t cols = (size_t)L.RU * L.RU * C * sizeof(float);
+    const size_t vals = (size_t)L.RV * L.RV * C * sizeof(double);
     size_t off = 0;
-    L.v = off; off = ct_align16(off + (size_t)L.RV * L.RV * C * sizeof(double));
-    L.T = off; off = ct_align16(off + (size_t)L.RT * L.RT * 3 * sizeof(double));
-    L.ws = off; off = ct_align16(off + (size_t)(2 * rs + 1) * (2 * rs + 1) * sizeof(double));
+    L.rsum = L.T = off; off = ct_align16(off + (rsum > tens ? rsum : tens));
+    L.u = L.v = off; off = ct_align16(off + (cols > vals ? cols : vals));
+    L.w1 = off; off = ct_align16(off + (size_t)(2 * rs + 1) * sizeof(double));
     L.wr = off; off = ct_align16(off + (size_t)(2 * rr + 1) * (2 * rr + 1) * sizeof(double));
-    L.u = off; off = ct_align16(off + (size_t)L.RU * L.RU * C * sizeof(float));
     L.kn = off; off = ct_align16(off + (size_t)L.RU * L.RU);
     L.vok = off; off = ct_align16(off + (size_t)L.RV * L.RV);
     L.total = off;
@@ -115,7 +122,8 @@ __global__ __launch_bounds__(kBlock) void ct_guide_kernel(CtArgs A) {
 
     double *v = reinterpret_cast<double *>(ct_smem + L.v);
     double *T = reinterpret_cast<double *>(ct_smem + L.T);
-    double *ws = reinterpret_cast<double *>(ct_smem + L.ws);
+    double *rsum = reinterpret_cast<double *>(ct_smem + L.rsum);
+    double *w1 = reinterpret_cast<double *>(ct_smem + L.w1);
     double *wr = reinterpret_cast<double *>(ct_smem + L.wr);
     float *u = reinterpret_cast<float *>(ct_smem + L.u);
     uint8_t *kn = ct_smem + L.kn;
@@ -123,9 +131,9 @@ __global__ __launch_bounds__(kBlock) void ct_guide_kernel(CtArgs A) {
     const int rs = A.rs, rr = A.rr, WS = 2 * rs + 1, WR = 2 * rr + 1;
     const int RU = L.RU, RV = L.RV, RT = L.RT;
 
-    for (int i = tid; i < WS * WS; i += kBlock) {
-        const int dx = i % WS - rs, dy = i / WS - rs;
-        ws[i] = exp(-(double)(dx * dx + dy * dy) / (2.0 * A.sigma * A.sigma));
+    for (int i = tid; i < WS; i += kBlock) {
+        const int d = i - rs;
+        w1[i] = exp(-(double)(d * d) / (2.0 * A.sigma * A.sigma));
     }
     for (int i = tid; i < WR * WR; i += kBlock) {
         const int dx = i % WR - rr, dy = i / WR - rr;
@@ -144,21 +152,43 @@ __global__ __launch_bounds__(kBlock) void ct_guide_kernel(CtArgs A) {
     }
     __syncthreads();
 
-    // v over the v region (centre of v-index (lx, ly) is u-index (lx + rs, ly + rs))
-    for (int i = tid; i < RV * RV; i += kBlock) {
-        const int lx = i % RV, ly = i / RV;
+    // row sums of the smoothing: for every row of the colour region and every
+    // column of the v region, sum_dx w(dx) 1_K u and sum_dx w(dx) 1_K
+    const int RS1 = C + 1;
+    for (int i = tid; i < RU * RV; i += kBlock) {
+        const int ry = i / RV, lx = i - ry * RV;
         double num[4] = {0.0, 0.0, 0.0, 0.0};
         double den = 0.0;
-        for (int dy = -rs; dy <= rs; ++dy)
-            for (int dx = -rs; dx <= rs; ++dx) {
-                const int ui = (ly + rs + dy) * RU + (lx + rs + dx);
-                if (!kn[ui]) continue;
-                const double w = ws[(dy + rs) * WS + dx + rs];
-                den += w;
+        for (int dx = -rs; dx <= rs; ++dx) {
+            const int ui = ry * RU + lx + rs + dx;
+            if (!kn[ui]) continue;
+            const double w = w1[dx + rs];
+            den += w;
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (c < C) num[c] += w * (double)u[ui * C + c];
-            }
+            for (int c = 0; c < 4; ++c)
+                if (c < C) num[c] += w * (double)u[ui * C + c];
+        }
+        double *o = rsum + (size_t)i * RS1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < C) o[c] = num[c];
+        o[C] = den;
+    }
+    __syncthreads();
+    // v over the v region: the column sums of the row sums (the v pixel (lx, ly)
+    // is centred on colour row ly + rs)
+    for (int i = tid; i < RV * RV; i += kBlock) {
+        const int ly = i / RV, lx = i - ly * RV;
+        double num[4] = {0.0, 0.0, 0.0, 0.0};
+        double den = 0.0;
+        for (int dy = -rs; dy <= rs; ++dy) {
+            const double w = w1[dy + rs];
+            const double *r = rsum + ((size_t)(ly + rs + dy) * RV + lx) * RS1;
+            den += w * r[C];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < C) num[c] += w * r[c];
+        }
         vok[i] = den > 0.0 ? 1 : 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
