@@ -34,7 +34,7 @@ def _frames(B, H, W, seed=5):
     return np.stack(imgs), lab, g, th
 
 
-def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0, engine=0):
+def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0, **launch):
     import torch
 
     import paper_1611_05319_amd as gf
@@ -42,7 +42,7 @@ def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0, engine=0):
     img, lab, g, th = _frames(B, H, W)
     rng = np.random.default_rng(77)
     omega = rng.normal(size=img.shape).astype(np.float32)
-    u, s, st, r = gpu_fill(img, lab, g, ghost=ghost, mu=mu, eps=eps, engine=engine)
+    u, s, st, r = gpu_fill(img, lab, g, ghost=ghost, mu=mu, eps=eps, **launch)
     gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g),
                               gf.Params(eps=eps, mu=mu, ghost=ghost))
     torch.cuda.synchronize()
@@ -70,10 +70,15 @@ def test_adjoint_small(ghost, eps):
     _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0, eps=eps)
 
 
-@pytest.mark.parametrize("engine", [0, 1])
-def test_adjoint_config5_full(engine):
-    banner(f"adjoint 16 x 512 x 512, forward engine {engine}")
-    st = _compare(16, 512, 512, engine=engine)
+# the forward launches: each engine at its defaults, and the global front at
+# 8 lanes per pixel and 2 workgroups per CU, the shape the autotuner picks for
+# this workload
+@pytest.mark.parametrize("launch", [{"engine": 0}, {"engine": 1},
+                                    {"engine": 1, "group": 8, "blocks_per_cu": 2}],
+                         ids=["tiled", "front", "front8x2"])
+def test_adjoint_config5_full(launch):
+    banner(f"adjoint 16 x 512 x 512, forward launch {launch}")
+    st = _compare(16, 512, 512, **launch)
     assert st["K"] >= 3
 
 
