@@ -662,13 +662,27 @@ __device__ inline int block_exclusive_scan(int v, int *s_wave, int *total) {
 }
 
 // Adjoint of one filled pixel x (shell k), one pass over its ball:
-//   u = (1/S) sum_j w_j v_j,  S = sum_j w_j,  log w_j = -a (g_perp . o_j)^2 - log|o_j|
+//   u = (1/S) sum_j w_j v_j,  S = sum_j w_j,  log w_j = -a t_j^2 - log|o_j|,
+//   t_j = g_perp . o_j (g unnormalised, as in the weight), o_j = R(theta) n_j
 //   du/dg = (1/S) sum_j w_j ((v_j - u) dlog w_j/dg + dv_j/dg)
 //         = (1/S) [sum_j w_j v_j dlw_j - u sum_j w_j dlw_j + sum_j w_j dv_j]
-// so every sum is accumulated in the same pass as S and u; |o_j| does not
-// depend on g (the rotation preserves length).  A second pass scatters
-// ubar(x) w_j / S times the bilinear basis values into the support pixels.
-// agg: this group's LDS patch of (2D + 1)^2 pixels x C floats, or nullptr.
+// and the guide gradient is ubar(x) . du/dg.  ubar(x) is known before the
+// pass, so each ghost value enters only as its projection e_j = ubar . v_j
+// (bilinear in the corners' projections, as v_j is in their colours).  |o_j|
+// does not depend on g (the rotation preserves length).  With c = cos theta,
+// s = sin theta, L = |g| and p_j = c o_x + s o_y (the offset along g), the
+// rotation's derivative d o / d theta = (-o_y, o_x), d theta/dg = (-s, c) / L
+// give
+//   dt_j/dgx = o_y - s p_j,   dt_j/dgy = c p_j - o_x,
+//   de_j/dg  = (s, -c) / L * (de_j/do_x o_y - de_j/do_y o_x),
+// so six scalar sums over the ball (S, sum w e, sum w e dlw, sum w dlw per
+// component, and sum w (e_x o_y - e_y o_x)) carry every channel.  Pass 1 is
+// the forward's geometry (exact, uncontracted: it decides the readable set);
+// the sums and the scatter may contract.  A second pass scatters
+// ubar(x) w_j / S times the bilinear basis values into the support pixels, in
+// binary32 (the precision of the gradient buffer).
+// agg: this group's LDS patch of (2D + 1)^2 floats, or nullptr; it lies over
+// the group's window, which pass 3 no longer reads.
 template <typename TS, int G>
 __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const short2 *off,
                                                          const double *rinv, int T, long long gidx,
@@ -682,10 +696,6 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
     const int C = A.C;
     const int WW = 2 * D + 1;  // the staged window: x at (D, D)
     float *GI = A.grad_img;
-    // ubar(x), loaded by the caller beside the window
-    double ub[4];
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) ub[ch] = (double)ubf[ch];
     const double gx = (double)gv.x, gy = (double)gv.y;
     const bool rot = A.ghost && (gx != 0.0 || gy != 0.0);
     double cs = 0.0, sn = 0.0, L = 1.0;
@@ -694,27 +704,26 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
         cs = gx / L;
         sn = gy / L;
     }
-    // pass 1: geometry and readable set (kept for the other passes); supports
-    // as window indices (every support lies inside the window; pixels outside
-    // the frame are staged as bystanders, hence unreadable)
-    double fxs[kPerLaneMax], fys[kPerLaneMax], q[kPerLaneMax];
+    // pass 1: geometry and readable set; the rotated offsets and the supports
+    // (as window indices: every support lies inside the window; pixels outside
+    // the frame are staged as bystanders, hence unreadable) are kept
+    double oxs[kPerLaneMax], oys[kPerLaneMax];
     int base[kPerLaneMax];
     unsigned rmask = 0, exmask = 0, eymask = 0;
     double qmin = INFINITY;
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
-        fxs[r] = fys[r] = 0.0;
-        q[r] = INFINITY;
+        oxs[r] = oys[r] = 0.0;
         base[r] = 0;
         const int t = l + r * G;
         if (t < T) {
             const short2 nm = off[t];
             double ox, oy;
             rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
+            oxs[r] = ox;
+            oys[r] = oy;
             const double fx0 = floor(ox), fy0 = floor(oy);
             const bool ex = (ox == fx0), ey = (oy == fy0);
-            fxs[r] = ex ? 0.0 : ox - fx0;
-            fys[r] = ey ? 0.0 : oy - fy0;
             exmask |= ex ? (1u << r) : 0u;
             eymask |= ey ? (1u << r) : 0u;
             const int b = (D + (int)fy0) * WW + (D + (int)fx0);
@@ -722,45 +731,35 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
             const int dx = ex ? 0 : 1, dy = ey ? 0 : WW;
             const bool rd = ((int)readable(wst[b], k) & (int)readable(wst[b + dx], k) &
                              (int)readable(wst[b + dy], k) & (int)readable(wst[b + dy + dx], k)) != 0;
-            const double tp = (-gy) * ox + gx * oy;
-            q[r] = A.a * tp * tp;
             if (rd) {
+                const double tp = (-gy) * ox + gx * oy;
                 rmask |= 1u << r;
-                qmin = fmin(qmin, q[r]);
+                qmin = fmin(qmin, A.a * tp * tp);
             }
         }
     }
     qmin = gmin<G>(qmin);
-    // pass 2: weights, values, value derivatives, all sums
+    // pass 2: weights, projected values and their derivatives, all sums
     double w[kPerLaneMax];
-    double Ssum = 0.0, Bx = 0.0, By = 0.0;
-    double Uc[4] = {0.0, 0.0, 0.0, 0.0}, Ax[4] = {0.0, 0.0, 0.0, 0.0}, Ay[4] = {0.0, 0.0, 0.0, 0.0};
-    double Dx[4] = {0.0, 0.0, 0.0, 0.0}, Dy[4] = {0.0, 0.0, 0.0, 0.0};
+    double Ssum = 0.0, Bx = 0.0, By = 0.0, P = 0.0, Ax = 0.0, Ay = 0.0, E = 0.0;
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
         w[r] = 0.0;
         if (rmask & (1u << r)) {
+#pragma clang fp contract(fast)
             const int t = l + r * G;
-            const short2 nm = off[t];
-            double ox, oy;
-            rot_offset(rot, cs, sn, nm.x, nm.y, ox, oy);
-            const double wr = exp(-(q[r] - qmin)) * rinv[t];
+            const double ox = oxs[r], oy = oys[r];
+            const double tp = (-gy) * ox + gx * oy;
+            const double wr = exp(qmin - A.a * tp * tp) * rinv[t];
             w[r] = wr;
             Ssum += wr;
-            double dox_dgx = 0.0, dox_dgy = 0.0, doy_dgx = 0.0, doy_dgy = 0.0;
-            if (rot) {  // o rotates with g: d(theta) = (c dgy - s dgx) / |g|
-                dox_dgx = sn * oy / L;
-                dox_dgy = -cs * oy / L;
-                doy_dgx = -sn * ox / L;
-                doy_dgy = cs * ox / L;
-            }
-            const double tp = (-gy) * ox + gx * oy;
-            const double dlx = -2.0 * A.a * tp * (oy + (-gy) * dox_dgx + gx * doy_dgx);
-            const double dly = -2.0 * A.a * tp * (-ox + (-gy) * dox_dgy + gx * doy_dgy);
+            const double pr = cs * ox + sn * oy;  // 0 without rotation
+            const double m2a = -2.0 * A.a * tp;
+            const double dlx = m2a * (oy - sn * pr), dly = m2a * (cs * pr - ox);
             Bx += wr * dlx;
             By += wr * dly;
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-            const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
+            const double wx1 = ox - floor(ox), wy1 = oy - floor(oy), wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
             const int i00 = base[r], i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : WW),
                       i11 = i01 + (ex ? 0 : 1);
             float c00[4], c10[4], c01[4], c11[4];
@@ -768,96 +767,91 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
             lds_colours<TS>(wcol + i10 * 4, c10);
             lds_colours<TS>(wcol + i01 * 4, c01);
             lds_colours<TS>(wcol + i11 * 4, c11);
+            double e00 = 0.0, e10 = 0.0, e01 = 0.0, e11 = 0.0;  // ubar . corner colour
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
-                    const double u00 = c00[ch], u10 = c10[ch], u01 = c01[ch], u11 = c11[ch];
-                    const double v = wx0 * wy0 * u00 + wx1 * wy0 * u10 + wx0 * wy1 * u01 +
-                                     wx1 * wy1 * u11;
-                    const double vpx = ex ? 0.0 : wy0 * (u10 - u00) + wy1 * (u11 - u01);
-                    const double vpy = ey ? 0.0 : wx0 * (u01 - u00) + wx1 * (u11 - u10);
-                    Uc[ch] += wr * v;
-                    Ax[ch] += wr * v * dlx;
-                    Ay[ch] += wr * v * dly;
-                    Dx[ch] += wr * (vpx * dox_dgx + vpy * doy_dgx);
-                    Dy[ch] += wr * (vpx * dox_dgy + vpy * doy_dgy);
+                    const double u = (double)ubf[ch];
+                    e00 += u * (double)c00[ch];
+                    e10 += u * (double)c10[ch];
+                    e01 += u * (double)c01[ch];
+                    e11 += u * (double)c11[ch];
                 }
             }
+            const double v = wy0 * (wx0 * e00 + wx1 * e10) + wy1 * (wx0 * e01 + wx1 * e11);
+            const double vpx = ex ? 0.0 : wy0 * (e10 - e00) + wy1 * (e11 - e01);
+            const double vpy = ey ? 0.0 : wx0 * (e01 - e00) + wx1 * (e11 - e10);
+            P += wr * v;
+            Ax += wr * v * dlx;
+            Ay += wr * v * dly;
+            E += wr * (vpx * oy - vpy * ox);
         }
     }
     Ssum = gsum<G>(Ssum);
-    Bx = gsum<G>(Bx);
-    By = gsum<G>(By);
     const double inv = 1.0 / Ssum;
-    double dgx = 0.0, dgy = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        if (ch < C) {
-            const double u = gsum<G>(Uc[ch]) * inv;
-            dgx += ub[ch] * (gsum<G>(Ax[ch]) - u * Bx + gsum<G>(Dx[ch])) * inv;
-            dgy += ub[ch] * (gsum<G>(Ay[ch]) - u * By + gsum<G>(Dy[ch])) * inv;
-        }
-    }
-    // pass 3: pass the adjoint to the bilinear supports.  With a small ball the
-    // contributions are first summed per support pixel in the group's LDS
-    // patch of (2D + 1)^2 pixels around x (laid out as the window), so each
-    // touched pixel takes one global atomic per channel instead of one per
-    // ghost point that reads it.
+    const double u = gsum<G>(P) * inv;  // ubar(x) . u(x)
+    const double Eg = rot ? gsum<G>(E) / L : 0.0;
+    const double dgx = (gsum<G>(Ax) - u * gsum<G>(Bx) + sn * Eg) * inv;
+    const double dgy = (gsum<G>(Ay) - u * gsum<G>(By) - cs * Eg) * inv;
+    // pass 3: pass the adjoint to the bilinear supports.  Support pixel y
+    // receives ubar(x) times the scalar sum over the ghost points of
+    // (w_j / S) times y's bilinear basis value.  With a small ball those
+    // scalars are first summed in the group's LDS patch of (2D + 1)^2 pixels
+    // around x (laid out as the window), so each touched pixel takes one
+    // global atomic per channel instead of one per ghost point that reads it.
     const long long fo = f * A.HW;
     if (agg) {
-        for (int i = l; i < WW * WW * C; i += G) agg[i] = 0.0f;
+        // the group's lanes share a wavefront, so its window reads above are
+        // done before the patch, laid over the window, is cleared
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int i = l; i < WW * WW; i += G) agg[i] = 0.0f;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
         for (int r = 0; r < kPerLaneMax; ++r) {
             if (rmask & (1u << r)) {
                 const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-                const double lam = w[r] * inv;
-                const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
-                const int j00 = base[r] * C;
-                const int j10 = j00 + (ex ? 0 : C), j01 = j00 + (ey ? 0 : WW * C),
-                          j11 = j01 + (ex ? 0 : C);
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    if (ch < C) {
-                        const double g = ub[ch] * lam;
-                        atomicAdd(&agg[j00 + ch], (float)(g * wx0 * wy0));
-                        if (!ex) atomicAdd(&agg[j10 + ch], (float)(g * wx1 * wy0));
-                        if (!ey) atomicAdd(&agg[j01 + ch], (float)(g * wx0 * wy1));
-                        if (!ex && !ey) atomicAdd(&agg[j11 + ch], (float)(g * wx1 * wy1));
-                    }
-                }
+                const float lam = (float)(w[r] * inv);
+                const float wx1 = (float)(oxs[r] - floor(oxs[r])), wy1 = (float)(oys[r] - floor(oys[r]));
+                const float wx0 = 1.0f - wx1, wy0 = 1.0f - wy1;
+                const int j00 = base[r];
+                const int j10 = j00 + (ex ? 0 : 1), j01 = j00 + (ey ? 0 : WW), j11 = j01 + (ex ? 0 : 1);
+                atomicAdd(&agg[j00], lam * wx0 * wy0);
+                if (!ex) atomicAdd(&agg[j10], lam * wx1 * wy0);
+                if (!ey) atomicAdd(&agg[j01], lam * wx0 * wy1);
+                if (!ex && !ey) atomicAdd(&agg[j11], lam * wx1 * wy1);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         for (int i = l; i < WW * WW; i += G) {
-            const int yy = Y - D + i / WW, xx = X - D + i % WW;
+            const float v = agg[i];
+            if (v != 0.0f) {  // a nonzero sum only lands on a support pixel, inside the frame
+                const int yy = Y - D + i / WW, xx = X - D + i % WW;
+                float *gp = GI + (fo + (long long)yy * W + xx) * C;
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                if (ch < C) {
-                    const float v = agg[i * C + ch];
-                    // a nonzero sum only lands on a support pixel, inside the frame
-                    if (v != 0.0f) unsafeAtomicAdd(&GI[(fo + (long long)yy * W + xx) * C + ch], v);
-                }
+                for (int ch = 0; ch < 4; ++ch)
+                    if (ch < C) unsafeAtomicAdd(gp + ch, ubf[ch] * v);
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // before the next window
     }
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
         if (!agg && (rmask & (1u << r))) {
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-            const double lam = w[r] * inv;
-            const double wx1 = fxs[r], wy1 = fys[r], wx0 = 1.0 - wx1, wy0 = 1.0 - wy1;
+            const float lam = (float)(w[r] * inv);
+            const float wx1 = (float)(oxs[r] - floor(oxs[r])), wy1 = (float)(oys[r] - floor(oys[r]));
+            const float wx0 = 1.0f - wx1, wy0 = 1.0f - wy1;
             const int by = base[r] / WW, bx = base[r] - by * WW;
             const long long i00 = fo + (long long)(Y - D + by) * W + (X - D + bx),
                             i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W), i11 = i01 + (ex ? 0 : 1);
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 if (ch < C) {
-                    const double g = ub[ch] * lam;
-                    unsafeAtomicAdd(&GI[i00 * C + ch], (float)(g * wx0 * wy0));
-                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], (float)(g * wx1 * wy0));
-                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], (float)(g * wx0 * wy1));
-                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], (float)(g * wx1 * wy1));
+                    const float g = ubf[ch] * lam;
+                    unsafeAtomicAdd(&GI[i00 * C + ch], g * wx0 * wy0);
+                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], g * wx1 * wy0);
+                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], g * wx0 * wy1);
+                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], g * wx1 * wy1);
                 }
             }
         }
@@ -870,10 +864,13 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
 }
 
 // Bytes of dynamic LDS per group of the adjoint's reverse shells: the
-// neighbourhood window, then the support patch
+// neighbourhood window, and over it, once pass 2 has read the window, the
+// support patch
 template <typename TS> __host__ __device__ inline int bwd_group_bytes(int D, int C) {
-    const int patch = D <= kAggMaxD ? (((2 * D + 1) * (2 * D + 1) * C * 4 + 15) & ~15) : 0;
-    return window_bytes<TS>(D) + patch;
+    (void)C;
+    const int patch = D <= kAggMaxD ? (((2 * D + 1) * (2 * D + 1) * 4 + 15) & ~15) : 0;
+    const int win = window_bytes<TS>(D);
+    return win > patch ? win : patch;
 }
 
 // Bytes of dynamic LDS the adjoint launch takes: the sorting bins, later the
@@ -890,7 +887,7 @@ template <typename TS> __host__ __device__ inline size_t bwd_dyn_lds(int G, int 
 // through to grad_img and clears grad_guide; (2) replay the shells from the
 // last to the first, one grid barrier apart.
 template <typename TS, int G>
-__global__ __launch_bounds__(kBlock, 2) void bwd_kernel(BwdArgs A) {
+__global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ short2 s_off[kMaxOffsets];
     __shared__ double s_rinv[kMaxOffsets];
@@ -984,7 +981,7 @@ __global__ __launch_bounds__(kBlock, 2) void bwd_kernel(BwdArgs A) {
     unsigned char *gbase = smem + gi * bwd_group_bytes<TS>(D, C);
     int32_t *w_st = reinterpret_cast<int32_t *>(gbase);
     TS *w_col = reinterpret_cast<TS *>(gbase + ((WN * 4 + 15) & ~15));
-    float *agg = reinterpret_cast<float *>(gbase + window_bytes<TS>(D));
+    float *agg = reinterpret_cast<float *>(gbase);
     for (int k = K - 1; k >= 0; --k) {
         const long long b0 = ld_ctl(A.offs, k), b1 = ld_ctl(A.offs, k + 1);
         const long long n = b1 - b0;
