@@ -45,7 +45,6 @@ __device__ inline bool data_term_ok(float2 g, double c2) {
 }
 
 constexpr int kItemCap = 512;  // front-list entries a workgroup stages per chunk
-constexpr int kAggMaxD = 4;    // adjoint: support patches up to (2*4+1)^2 pixels in LDS
 
 // LDS staging of list appends: one global atomic per workgroup per flush
 struct Stage {
@@ -681,8 +680,8 @@ __device__ inline int block_exclusive_scan(int v, int *s_wave, int *total) {
 // the sums and the scatter may contract.  A second pass scatters
 // ubar(x) w_j / S times the bilinear basis values into the support pixels, in
 // binary32 (the precision of the gradient buffer).
-// agg: this group's LDS patch of (2D + 1)^2 floats, or nullptr; it lies over
-// the group's window, which pass 3 no longer reads.
+// agg: this group's LDS patch of (2D + 1)^2 floats; it lies over the group's
+// window, which pass 3 no longer reads.
 template <typename TS, int G>
 __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const short2 *off,
                                                          const double *rinv, int T, long long gidx,
@@ -795,67 +794,43 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
     const double dgy = (gsum<G>(Ay) - u * gsum<G>(By) - cs * Eg) * inv;
     // pass 3: pass the adjoint to the bilinear supports.  Support pixel y
     // receives ubar(x) times the scalar sum over the ghost points of
-    // (w_j / S) times y's bilinear basis value.  With a small ball those
-    // scalars are first summed in the group's LDS patch of (2D + 1)^2 pixels
-    // around x (laid out as the window), so each touched pixel takes one
-    // global atomic per channel instead of one per ghost point that reads it.
+    // (w_j / S) times y's bilinear basis value.  Those scalars are first
+    // summed in the group's LDS patch of (2D + 1)^2 pixels around x (laid out
+    // as the window), so each touched pixel takes one global atomic per
+    // channel instead of one per ghost point that reads it.
     const long long fo = f * A.HW;
-    if (agg) {
-        // the group's lanes share a wavefront, so its window reads above are
-        // done before the patch, laid over the window, is cleared
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int i = l; i < WW * WW; i += G) agg[i] = 0.0f;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-#pragma unroll
-        for (int r = 0; r < kPerLaneMax; ++r) {
-            if (rmask & (1u << r)) {
-                const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
-                const float lam = (float)(w[r] * inv);
-                const float wx1 = (float)(oxs[r] - floor(oxs[r])), wy1 = (float)(oys[r] - floor(oys[r]));
-                const float wx0 = 1.0f - wx1, wy0 = 1.0f - wy1;
-                const int j00 = base[r];
-                const int j10 = j00 + (ex ? 0 : 1), j01 = j00 + (ey ? 0 : WW), j11 = j01 + (ex ? 0 : 1);
-                atomicAdd(&agg[j00], lam * wx0 * wy0);
-                if (!ex) atomicAdd(&agg[j10], lam * wx1 * wy0);
-                if (!ey) atomicAdd(&agg[j01], lam * wx0 * wy1);
-                if (!ex && !ey) atomicAdd(&agg[j11], lam * wx1 * wy1);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int i = l; i < WW * WW; i += G) {
-            const float v = agg[i];
-            if (v != 0.0f) {  // a nonzero sum only lands on a support pixel, inside the frame
-                const int yy = Y - D + i / WW, xx = X - D + i % WW;
-                float *gp = GI + (fo + (long long)yy * W + xx) * C;
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch)
-                    if (ch < C) unsafeAtomicAdd(gp + ch, ubf[ch] * v);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // before the next window
-    }
+    // the group's lanes share a wavefront, so its window reads above are done
+    // before the patch, laid over the window, is cleared
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int i = l; i < WW * WW; i += G) agg[i] = 0.0f;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int r = 0; r < kPerLaneMax; ++r) {
-        if (!agg && (rmask & (1u << r))) {
+        if (rmask & (1u << r)) {
             const bool ex = (exmask >> r) & 1u, ey = (eymask >> r) & 1u;
             const float lam = (float)(w[r] * inv);
             const float wx1 = (float)(oxs[r] - floor(oxs[r])), wy1 = (float)(oys[r] - floor(oys[r]));
             const float wx0 = 1.0f - wx1, wy0 = 1.0f - wy1;
-            const int by = base[r] / WW, bx = base[r] - by * WW;
-            const long long i00 = fo + (long long)(Y - D + by) * W + (X - D + bx),
-                            i10 = i00 + (ex ? 0 : 1), i01 = i00 + (ey ? 0 : W), i11 = i01 + (ex ? 0 : 1);
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                if (ch < C) {
-                    const float g = ubf[ch] * lam;
-                    unsafeAtomicAdd(&GI[i00 * C + ch], g * wx0 * wy0);
-                    if (!ex) unsafeAtomicAdd(&GI[i10 * C + ch], g * wx1 * wy0);
-                    if (!ey) unsafeAtomicAdd(&GI[i01 * C + ch], g * wx0 * wy1);
-                    if (!ex && !ey) unsafeAtomicAdd(&GI[i11 * C + ch], g * wx1 * wy1);
-                }
-            }
+            const int j00 = base[r];
+            const int j10 = j00 + (ex ? 0 : 1), j01 = j00 + (ey ? 0 : WW), j11 = j01 + (ex ? 0 : 1);
+            atomicAdd(&agg[j00], lam * wx0 * wy0);
+            if (!ex) atomicAdd(&agg[j10], lam * wx1 * wy0);
+            if (!ey) atomicAdd(&agg[j01], lam * wx0 * wy1);
+            if (!ex && !ey) atomicAdd(&agg[j11], lam * wx1 * wy1);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int i = l; i < WW * WW; i += G) {
+        const float v = agg[i];
+        if (v != 0.0f) {  // a nonzero sum only lands on a support pixel, inside the frame
+            const int yy = Y - D + i / WW, xx = X - D + i % WW;
+            float *gp = GI + (fo + (long long)yy * W + xx) * C;
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                if (ch < C) unsafeAtomicAdd(gp + ch, ubf[ch] * v);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // before the next window
     if (l == 0) {
         A.grad_guide[gidx * 2 + 0] = (float)dgx;
         A.grad_guide[gidx * 2 + 1] = (float)dgy;
@@ -864,13 +839,11 @@ __device__ __attribute__((always_inline)) void bwd_pixel(const BwdArgs &A, const
 }
 
 // Bytes of dynamic LDS per group of the adjoint's reverse shells: the
-// neighbourhood window, and over it, once pass 2 has read the window, the
-// support patch
+// neighbourhood window; the support patch (one float per window pixel) lies
+// over its states once pass 2 has read the window
 template <typename TS> __host__ __device__ inline int bwd_group_bytes(int D, int C) {
     (void)C;
-    const int patch = D <= kAggMaxD ? (((2 * D + 1) * (2 * D + 1) * 4 + 15) & ~15) : 0;
-    const int win = window_bytes<TS>(D);
-    return win > patch ? win : patch;
+    return window_bytes<TS>(D);
 }
 
 // Bytes of dynamic LDS the adjoint launch takes: the sorting bins, later the
@@ -972,48 +945,74 @@ __global__ __launch_bounds__(kBlock, 3) void bwd_kernel(BwdArgs A) {
         if (cb + kBwdBins >= K) break;
     }
     // ---- reverse shells ---------------------------------------------------------
+    // The shell map and the forward's colours do not change here, so a shell's
+    // list entries, guides and each group's first window are fetched before
+    // the barrier that opens the shell; only the arriving adjoint ubar(x)
+    // waits for it.
     const int T = s_T;
     const int nG = kBlock / G;
     const int gi = tid / G, l = tid & (G - 1);
     const int D = (int)ceil(A.eps);
-    const bool use_agg = D <= kAggMaxD;
     const int WN = (2 * D + 1) * (2 * D + 1);
     unsigned char *gbase = smem + gi * bwd_group_bytes<TS>(D, C);
     int32_t *w_st = reinterpret_cast<int32_t *>(gbase);
     TS *w_col = reinterpret_cast<TS *>(gbase + ((WN * 4 + 15) & ~15));
     float *agg = reinterpret_cast<float *>(gbase);
+    // this workgroup's share [lo, hi) of shell k's entries in order
+    auto share = [&](int k, long long &lo, long long &hi) {
+        const long long b0 = ld_ctl(A.offs, k), n = ld_ctl(A.offs, k + 1) - b0;
+        lo = b0 + n * lw / nblk;
+        hi = b0 + n * (lw + 1) / nblk;
+    };
+    // entries [c0, c0 + cn) and their guides into LDS (between two workgroup barriers)
+    auto fetch_items = [&](long long c0, int cn) {
+        __syncthreads();
+        for (int i = tid; i < cn; i += kBlock) {
+            const int gidx = A.order[c0 + i];
+            s_item[i] = gidx;
+            s_gd[i] = reinterpret_cast<const float2 *>(A.guide)[gidx];
+        }
+        __syncthreads();
+    };
+    auto fetch_window = [&](long long gidx) {
+        const long long f = gidx / A.HW;
+        const int p = (int)(gidx - f * A.HW);
+        const int y = p / A.W, x = p - y * A.W;
+        stage_window<TS, G, 8>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.img) + f * A.HW * C,
+                               A.W, A.H, C, x, y, D, w_st, w_col, l);
+    };
+    long long lo2 = 0, hi2 = 0;
+    if (K > 0) {
+        share(K - 1, lo2, hi2);
+        const int cn = (int)min((long long)kItemCap, hi2 - lo2);
+        fetch_items(lo2, cn);
+        if (gi < cn) fetch_window(s_item[gi]);
+    }
     for (int k = K - 1; k >= 0; --k) {
-        const long long b0 = ld_ctl(A.offs, k), b1 = ld_ctl(A.offs, k + 1);
-        const long long n = b1 - b0;
-        const long long lo2 = b0 + n * lw / nblk, hi2 = b0 + n * (lw + 1) / nblk;
         for (long long c0 = lo2; c0 < hi2; c0 += kItemCap) {  // items and guides via LDS
             const int cn = (int)min((long long)kItemCap, hi2 - c0);
-            __syncthreads();
-            for (int i = tid; i < cn; i += kBlock) {
-                const int gidx = A.order[c0 + i];
-                s_item[i] = gidx;
-                s_gd[i] = reinterpret_cast<const float2 *>(A.guide)[gidx];
-            }
-            __syncthreads();
+            if (c0 != lo2) fetch_items(c0, cn);
             for (int base = 0; base < cn; base += nG) {
                 const int item = base + gi;
                 if (item < cn) {
                     const long long gidx = s_item[item];
-                    const long long f = gidx / A.HW;
-                    const int p = (int)(gidx - f * A.HW);
-                    const int y = p / A.W, x = p - y * A.W;
                     // the adjoint arriving at x is complete (every shell after k
                     // is done); its load is in flight with the window's
                     float ubf[4];
 #pragma unroll
                     for (int ch = 0; ch < 4; ++ch) ubf[ch] = A.grad_img[gidx * C + min(ch, C - 1)];
-                    stage_window<TS, G, 8>(A.shell + f * A.HW, reinterpret_cast<const TS *>(A.img) + f * A.HW * C,
-                                           A.W, A.H, C, x, y, D, w_st, w_col, l);
-                    bwd_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l,
-                                     use_agg ? agg : nullptr, D, w_st, w_col, ubf);
+                    if (c0 != lo2 || base != 0) fetch_window(gidx);
+                    bwd_pixel<TS, G>(A, s_off, s_rinv, T, gidx, s_gd[item], k, l, agg, D, w_st,
+                                     w_col, ubf);
                 }
                 GF_TCNT(6, 1);
             }
+        }
+        if (k > 0) {  // the next shell's first entries and windows
+            share(k - 1, lo2, hi2);
+            const int cn = (int)min((long long)kItemCap, hi2 - lo2);
+            fetch_items(lo2, cn);
+            if (gi < cn) fetch_window(s_item[gi]);
         }
         GF_TACC(4);
         grid_sync(A.ctl, grid);
