@@ -64,7 +64,7 @@ def _compare(B, H, W, ghost=True, mu=50.0, eps=3.0, **launch):
 
 
 @pytest.mark.parametrize("ghost", [True, False])
-@pytest.mark.parametrize("eps", [3.0, 3.6, 5.0])  # windows of radius 3, 4 and 5
+@pytest.mark.parametrize("eps", [3.0, 3.6, 5.0, 6.0, 9.0])  # windows of radius 3 to 9; 8 to 64 lanes
 def test_adjoint_small(ghost, eps):
     banner(f"adjoint 2 x 96 x 128 ghost={ghost} eps={eps}")
     _compare(2, 96, 128, ghost=ghost, mu=50.0 if ghost else 5.0, eps=eps)
