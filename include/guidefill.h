@@ -193,7 +193,9 @@ gf_status gf_fill(const void *img_in, void *img_out, int H, int W, int C, gf_dty
  *               the fill propagates to them; filled hole pixels get 0).  May
  *               equal grad_out.
  *   grad_guide  B*H*W*2 binary32: dL/d guide on filled pixels, 0 elsewhere.
- *   p           the forward's parameters (eps, mu, ghost are used).
+ *   p           the forward's parameters (eps, mu, ghost are used; the launch
+ *               shape is the adjoint's own: the narrowest lane group that holds
+ *               the ball, two workgroups per CU).
  *   workspace   >= gf_backward_workspace_size(...) bytes, 256-byte aligned,
  *               zeroed before its first use (as for the forward).
  * Returns GF_OK or GF_EINVAL / GF_EUNSUPPORTED / GF_EDEVICE.
