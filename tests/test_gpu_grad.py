@@ -82,6 +82,40 @@ def test_adjoint_config5_full(launch):
     assert st["K"] >= 3
 
 
+@pytest.mark.parametrize("ghost", [True, False])
+def test_adjoint_binary16_storage(ghost):
+    """The adjoint of a binary16-storage fill (it reads the forward's binary16
+    colours) against the oracle's adjoint at the oracle's own binary16 fill.
+    The two fills agree bit for bit (FP64 tensor-product values, one rounding
+    to binary16 each; see the binary16 parity tests), which is asserted first,
+    so both adjoints see the same colours."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner(f"adjoint, binary16 storage, ghost={ghost}")
+    img, lab, g, th = _frames(2, 96, 128, seed=11)
+    img16 = img.astype(np.float16)
+    mu = 50.0 if ghost else 5.0
+    u, s, st, r = gpu_fill(img16.astype(np.float32), lab, g, ghost=ghost, mu=mu,
+                           dtype=torch.float16)
+    ref = oracle.fill(img16.astype(np.float64), lab, g, mu=mu, ghost=ghost, storage="f16")
+    np.testing.assert_array_equal(s, ref.shell)
+    np.testing.assert_array_equal(u, ref.u)
+    omega = np.random.default_rng(79).normal(size=img.shape).astype(np.float32)
+    gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g),
+                              gf.Params(mu=mu, ghost=ghost))
+    torch.cuda.synchronize()
+    gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
+    ri, rg = oracle.adjoint(lab, g, ref.u, ref.shell, omega.astype(np.float64), mu=mu, ghost=ghost)
+    for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
+        err = np.abs(a - b)
+        rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        banner(f"grad {name}: max abs {err.max():.2e} rel L2 {rel_l2:.2e}")
+        assert err.max() <= 1e-4
+        assert rel_l2 <= 1e-5
+
+
 def test_adjoint_replays_given_shell_count():
     """K passed explicitly (the forward's statistic) equals K taken from the
     map; a smaller K is the adjoint of a fill stopped after K shells."""
