@@ -674,8 +674,8 @@ __device__ inline int block_exclusive_scan(int v, int *s_wave, int *total) {
 // give
 //   dt_j/dgx = o_y - s p_j,   dt_j/dgy = c p_j - o_x,
 //   de_j/dg  = (s, -c) / L * (de_j/do_x o_y - de_j/do_y o_x),
-// so six scalar sums over the ball (S, sum w e, sum w e dlw, sum w dlw per
-// component, and sum w (e_x o_y - e_y o_x)) carry every channel.  Pass 1 is
+// so seven scalar sums over the ball (S, sum w e, sum w e dlw and sum w dlw
+// for each component of g, and sum w (e_x o_y - e_y o_x)) carry every channel.  Pass 1 is
 // the forward's geometry (exact, uncontracted: it decides the readable set);
 // the sums and the scatter may contract.  A second pass scatters
 // ubar(x) w_j / S times the bilinear basis values into the support pixels, in
