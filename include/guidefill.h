@@ -244,9 +244,11 @@ gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p,
  *   p           as for gf_fill_batched; p->max_shells bounds the shells;
  *               p->c2 must be < 0 (GF_EUNSUPPORTED otherwise).
  * Workspace: gf_coherence_workspace_size bytes, zeroed before first use.
- * Unlike the other fills this call is synchronous: it reads each shell's
- * count back to the host to decide whether to go on (one stream
- * synchronisation per shell), and returns when the fill has finished.
+ * Unlike the other fills this call is synchronous: it enqueues the shells in
+ * batches of 4 and reads their counts back to the host to decide whether to
+ * go on (one stream synchronisation per batch; a shell enqueued after the
+ * fill has finished or stalled changes nothing), and returns when the fill
+ * has finished.
  */
 size_t gf_coherence_workspace_size(int B, int H, int W, int C, gf_dtype dt, const gf_params *p);
 

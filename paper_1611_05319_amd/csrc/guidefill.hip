@@ -628,6 +628,12 @@ struct CtLayout {
     size_t fill, label, guide, step, stats, bad, total;
 };
 
+// Shells the comparison mode enqueues between two host reads of their
+// statistics.  A shell enqueued after the fill is over changes nothing (with
+// the state unchanged, the tensor field and the shell's fill are those of the
+// shell before, which filled nothing), so a batch only ends early in time.
+constexpr int kCtBatch = 4;
+
 bool ct_layout(int B, int H, int W, int C, int dt, const gf_params *p, CtLayout &L) {
     gf_params p1 = *p;
     p1.max_shells = 1;
@@ -639,7 +645,8 @@ bool ct_layout(int B, int H, int W, int C, int dt, const gf_params *p, CtLayout 
     L.label = off; off += align256(np);
     L.guide = off; off += align256(np * 2 * sizeof(float));
     L.step = off; off += align256(np * sizeof(int32_t));
-    L.stats = off; off += align256((size_t)(GF_STAT_FRAME0 + GF_STAT_PER_FRAME * B) * sizeof(int32_t));
+    L.stats = off;
+    off += align256((size_t)kCtBatch * (GF_STAT_FRAME0 + GF_STAT_PER_FRAME * B) * sizeof(int32_t));
     L.bad = off; off += 256;
     L.total = off;
     return true;
@@ -746,44 +753,55 @@ gf_status gf_fill_coherence(const void *img_in, void *img_out, int B, int H, int
 
     gf_params p1 = *p;
     p1.max_shells = 1;
-    std::vector<int32_t> step_stats(nstat), total(nstat, 0);
+    std::vector<int32_t> step_stats((size_t)kCtBatch * nstat), total(nstat, 0);
     int k = 0;
-    for (;;) {
-        if (p->max_shells > 0 && k >= p->max_shells) break;
-        void *kargs[] = {&A};
-        e = hipLaunchKernel(kfn, dim3((unsigned)ngrid), dim3(kBlock), kargs, lds, s);
-        if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
-        st = fill_batched(img_out, img_out, B, H, W, C, dt, label_w, guide_w, &p1, step, stats_step,
-                          nullptr, nullptr, nullptr, 0, ws + L.fill, L.label - L.fill, stream);
-        if (st != GF_OK) return st;
-        hipLaunchKernelGGL(ct_commit_kernel, dim3(egrid), dim3(kBlock), 0, s, label_w, step,
-                           shell_out, guide_w, guide_used, NP, k);
-        e = hipGetLastError();
-        if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
-        e = hipMemcpyAsync(step_stats.data(), stats_step, nstat * sizeof(int32_t),
+    for (bool more = true; more;) {
+        int n = kCtBatch;
+        if (p->max_shells > 0) n = std::min(n, p->max_shells - k);
+        if (n <= 0) break;
+        for (int j = 0; j < n; ++j) {  // shells k .. k + n - 1: guide, one-shell fill, commit
+            void *kargs[] = {&A};
+            e = hipLaunchKernel(kfn, dim3((unsigned)ngrid), dim3(kBlock), kargs, lds, s);
+            if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
+            st = fill_batched(img_out, img_out, B, H, W, C, dt, label_w, guide_w, &p1, step,
+                              stats_step + (size_t)j * nstat, nullptr, nullptr, nullptr, 0,
+                              ws + L.fill, L.label - L.fill, stream);
+            if (st != GF_OK) return st;
+            hipLaunchKernelGGL(ct_commit_kernel, dim3(egrid), dim3(kBlock), 0, s, label_w, step,
+                               shell_out, guide_w, guide_used, NP, k + j);
+            e = hipGetLastError();
+            if (e != hipSuccess) { set_err("hipLaunchKernel", e); return GF_EDEVICE; }
+        }
+        e = hipMemcpyAsync(step_stats.data(), stats_step, (size_t)n * nstat * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { set_err("shell statistics", e); return GF_EDEVICE; }
-        if (k == 0) {
-            total[GF_STAT_HOLE] = step_stats[GF_STAT_HOLE];
-            total[GF_STAT_WORKGROUPS] = step_stats[GF_STAT_WORKGROUPS];
-            for (int f = 0; f < B; ++f)
-                total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2] =
-                    step_stats[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2];
+        for (int j = 0; j < n && more; ++j) {
+            const int32_t *ss = step_stats.data() + (size_t)j * nstat;
+            if (k == 0) {
+                total[GF_STAT_HOLE] = ss[GF_STAT_HOLE];
+                total[GF_STAT_WORKGROUPS] = ss[GF_STAT_WORKGROUPS];
+                for (int f = 0; f < B; ++f)
+                    total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2] =
+                        ss[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 2];
+            }
+            total[GF_STAT_SYNC_TIMEOUT] |= ss[GF_STAT_SYNC_TIMEOUT];
+            total[GF_STAT_MAX_FRONT] = std::max(total[GF_STAT_MAX_FRONT], ss[GF_STAT_MAX_FRONT]);
+            const int filled = ss[GF_STAT_FILLED];
+            if (filled == 0) {  // a stall, or nothing left: the shells after it changed nothing
+                more = false;
+                break;
+            }
+            total[GF_STAT_FILLED] += filled;
+            total[GF_STAT_SHELLS] = k + 1;
+            for (int f = 0; f < B; ++f) {
+                const int ff = ss[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1];
+                total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f] += ff > 0 ? 1 : 0;
+                total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1] += ff;
+            }
+            ++k;
+            if (total[GF_STAT_FILLED] >= total[GF_STAT_HOLE]) more = false;
         }
-        total[GF_STAT_SYNC_TIMEOUT] |= step_stats[GF_STAT_SYNC_TIMEOUT];
-        total[GF_STAT_MAX_FRONT] = std::max(total[GF_STAT_MAX_FRONT], step_stats[GF_STAT_MAX_FRONT]);
-        const int filled = step_stats[GF_STAT_FILLED];
-        if (filled == 0) break;
-        total[GF_STAT_FILLED] += filled;
-        total[GF_STAT_SHELLS] = k + 1;
-        for (int f = 0; f < B; ++f) {
-            const int ff = step_stats[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1];
-            total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f] += ff > 0 ? 1 : 0;
-            total[GF_STAT_FRAME0 + GF_STAT_PER_FRAME * f + 1] += ff;
-        }
-        ++k;
-        if (total[GF_STAT_FILLED] >= total[GF_STAT_HOLE]) break;
     }
     int32_t nbad = 0;
     e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
