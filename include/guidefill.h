@@ -242,7 +242,9 @@ gf_status gf_tile_geometry(int H, int W, int C, gf_dtype dt, const gf_params *p,
  *               pixel was filled with (0 elsewhere); sign as computed
  *               (gx > 0, or gx == 0 and gy > 0).
  *   p           as for gf_fill_batched; p->max_shells bounds the shells;
- *               p->c2 must be < 0 (GF_EUNSUPPORTED otherwise).
+ *               p->c2 must be < 0 (GF_EUNSUPPORTED otherwise); each shell is
+ *               one fill launch, on the tiled engine with one shell per pass
+ *               unless p->pass_shells is set.
  * Workspace: gf_coherence_workspace_size bytes, zeroed before first use.
  * Unlike the other fills this call is synchronous: it enqueues the shells in
  * batches of 4 and reads their counts back to the host to decide whether to

@@ -634,9 +634,18 @@ struct CtLayout {
 // shell before, which filled nothing), so a batch only ends early in time.
 constexpr int kCtBatch = 4;
 
-bool ct_layout(int B, int H, int W, int C, int dt, const gf_params *p, CtLayout &L) {
+// the comparison mode's one-shell fills: one shell per launch, and on the
+// tiled engine (unless the caller sets it) one shell per pass, so the tile
+// windows carry a halo of ceil(eps) only (2.15 -> 2.09 ms at 1080p)
+gf_params ct_fill_params(const gf_params *p) {
     gf_params p1 = *p;
     p1.max_shells = 1;
+    if (p1.pass_shells == 0) p1.pass_shells = 1;
+    return p1;
+}
+
+bool ct_layout(int B, int H, int W, int C, int dt, const gf_params *p, CtLayout &L) {
+    const gf_params p1 = ct_fill_params(p);
     const size_t fw = workspace_bytes(B, H, W, C, dt, &p1);
     if (fw == 0) return false;
     const size_t np = (size_t)B * H * W;
@@ -751,8 +760,7 @@ gf_status gf_fill_coherence(const void *img_in, void *img_out, int B, int H, int
     const long long ngrid = (long long)B * A.tiles_x * A.tiles_y;
     if (ngrid >= (1ll << 31)) return GF_EUNSUPPORTED;
 
-    gf_params p1 = *p;
-    p1.max_shells = 1;
+    const gf_params p1 = ct_fill_params(p);
     std::vector<int32_t> step_stats((size_t)kCtBatch * nstat), total(nstat, 0);
     int k = 0;
     for (bool more = true; more;) {

@@ -230,7 +230,9 @@ def test_coherence_rejects_bad_arguments(lib):
     fake = ctypes.c_void_p(1 << 20)
     p = gf.Params(ghost=False).c_struct()
     n = lib.gf_coherence_workspace_size(2, 40, 50, 3, 0, ctypes.byref(p))
-    nf = lib.gf_workspace_size(2, 40, 50, 3, 0, ctypes.byref(p))
+    # its one-shell fills run one shell per pass
+    p1 = gf.Params(ghost=False, max_shells=1, pass_shells=1).c_struct()
+    nf = lib.gf_workspace_size(2, 40, 50, 3, 0, ctypes.byref(p1))
     assert n % 256 == 0 and n >= nf + 2 * 40 * 50 * (1 + 8 + 4)
     assert lib.gf_coherence_workspace_size(0, 40, 50, 3, 0, ctypes.byref(p)) == 0
 
