@@ -113,14 +113,17 @@ def test_batch_and_binary16():
 
 
 def test_other_scales_and_max_shells():
-    banner("coherence sigma 1.5 rho 3, max_shells 2")
+    banner("coherence sigma 1.5 rho 3, max_shells 2, 5 and 8")
     rng = np.random.default_rng(5)
     img, lab, _ = syn.random_tiny(rng, 60, 70, C=2, p_hole=0.4, p_bystander=0.0)
     _compare(img, lab, sigma=1.5, rho=3.0, Lambda=1e-3)
-    u, s, st, g = _gpu(img, lab, max_shells=2)
-    ref = oracle.coherence_fill(img, lab, max_shells=2, storage="f32", guide_f32=True)
-    np.testing.assert_array_equal(s, ref.shell)
-    assert st["K"] == 2
+    # the fill takes 5 shells: 2 stop within the first batch of enqueued shells,
+    # 5 in the second, 8 is never reached
+    for m in (2, 5, 8):
+        u, s, st, g = _gpu(img, lab, max_shells=m)
+        ref = oracle.coherence_fill(img, lab, max_shells=m, storage="f32", guide_f32=True)
+        np.testing.assert_array_equal(s, ref.shell)
+        assert st["K"] == min(m, int(ref.shell.max()) + 1)
 
 
 def test_kink_example_first_shell():
