@@ -82,6 +82,35 @@ def test_adjoint_config5_full(launch):
     assert st["K"] >= 3
 
 
+@pytest.mark.parametrize("C,eps", [(1, 3.0), (2, 4.5), (4, 3.0)])
+def test_adjoint_channels_bystanders_random_guides(C, eps):
+    """Channel counts other than 3, ragged sizes, bystanders, zero guides
+    (the lattice ball) and guides of random magnitude."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner(f"adjoint random tiny C={C} eps={eps}")
+    rng = np.random.default_rng([31, C])
+    img, lab, g = syn.random_tiny(rng, 67, 101, C=C, p_hole=0.35, p_bystander=0.1)
+    g = g.astype(np.float32)
+    u, s, st, r = gpu_fill(img, lab, g, eps=eps)
+    ref = oracle.fill(img, lab, g, eps=eps)
+    np.testing.assert_array_equal(s, ref.shell)
+    assert_colour_parity(u, ref.u, ref.shell)
+    omega = np.random.default_rng([32, C]).normal(size=img.shape).astype(np.float32)
+    gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g), gf.Params(eps=eps))
+    torch.cuda.synchronize()
+    gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
+    ri, rg = oracle.adjoint(lab, g, ref.u, ref.shell, omega.astype(np.float64), eps=eps)
+    for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
+        err = np.abs(a - b)
+        rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        banner(f"grad {name}: max abs {err.max():.2e} rel L2 {rel_l2:.2e}")
+        assert err.max() <= 1e-4
+        assert rel_l2 <= 1e-5
+
+
 @pytest.mark.parametrize("ghost", [True, False])
 def test_adjoint_binary16_storage(ghost):
     """The adjoint of a binary16-storage fill (it reads the forward's binary16
