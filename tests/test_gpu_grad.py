@@ -111,6 +111,36 @@ def test_adjoint_channels_bystanders_random_guides(C, eps):
         assert rel_l2 <= 1e-5
 
 
+@pytest.mark.parametrize("order", [{"c": 0.05}, {"c2": 0.3}], ids=["smart", "ready2"])
+def test_adjoint_after_other_orders(order):
+    """The adjoint needs only the shell map: after a smart-order fill
+    (eqn:ready) or one held back by the data term (eqn:ready2) it matches the
+    oracle's adjoint at the oracle's fill in that order."""
+    import torch
+
+    import paper_1611_05319_amd as gf
+
+    banner(f"adjoint after {order}")
+    rng = np.random.default_rng(33)
+    img, lab, g = syn.random_tiny(rng, 67, 101, C=3, p_hole=0.35, p_bystander=0.05)
+    g = g.astype(np.float32)
+    u, s, st, r = gpu_fill(img, lab, g, **order)
+    ref = oracle.fill(img, lab, g, **order)
+    np.testing.assert_array_equal(s, ref.shell)
+    assert_colour_parity(u, ref.u, ref.shell)
+    omega = np.random.default_rng(34).normal(size=img.shape).astype(np.float32)
+    gi, gg = gf.fill_backward(to_dev(omega), r, to_dev(lab), to_dev(g), gf.Params(**order))
+    torch.cuda.synchronize()
+    gi, gg = gi.cpu().numpy().astype(np.float64), gg.cpu().numpy().astype(np.float64)
+    ri, rg = oracle.adjoint(lab, g, ref.u, ref.shell, omega.astype(np.float64))
+    for name, a, b in (("img", gi, ri), ("guide", gg, rg)):
+        err = np.abs(a - b)
+        rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        banner(f"grad {name}: max abs {err.max():.2e} rel L2 {rel_l2:.2e}")
+        assert err.max() <= 1e-4
+        assert rel_l2 <= 1e-5
+
+
 @pytest.mark.parametrize("ghost", [True, False])
 def test_adjoint_binary16_storage(ghost):
     """The adjoint of a binary16-storage fill (it reads the forward's binary16
