@@ -139,16 +139,23 @@ __global__ __launch_bounds__(kBlock) void ct_guide_kernel(CtArgs A) {
         const int dx = i % WR - rr, dy = i / WR - rr;
         wr[i] = exp(-(double)(dx * dx + dy * dy) / (2.0 * A.rho * A.rho));
     }
-    // colours and known flags of the u region
+    // colours and known flags of the u region (a pixel's label and colours
+    // are loaded together, and several pixels' loads are in flight at once)
     const TS *img = static_cast<const TS *>(A.img) + (long long)f * A.HW * C;
     const int ux0 = x0 - rr - 1 - rs, uy0 = y0 - rr - 1 - rs;
+#pragma unroll 4
     for (int i = tid; i < RU * RU; i += kBlock) {
         const int gx = ux0 + i % RU, gy = uy0 + i / RU;
         const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-        const long long q = (long long)gy * W + gx;
+        const long long q = in ? (long long)gy * W + gx : 0;
+        float cv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cv[c] = (float)load_px<TS>(img + q * C + min(c, C - 1));
         const bool k = in && lab[q] == 0;
         kn[i] = k ? 1 : 0;
-        for (int c = 0; c < C; ++c) u[i * C + c] = k ? (float)load_px<TS>(img + q * C + c) : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < C) u[i * C + c] = k ? cv[c] : 0.0f;
     }
     __syncthreads();
 
