@@ -233,24 +233,48 @@ __global__ __launch_bounds__(kBlock) void ct_guide_kernel(CtArgs A) {
     }
     __syncthreads();
 
-    // J and the guide at the front pixels
-    if (front) {
-        const int lx = px - x0, ly = py - y0;
+    // J and the guide at the front pixels: the tile's front pixels are listed
+    // (in the v region, which is no longer read), and each is taken by a
+    // group of kJLanes lanes, every lane summing a share of the rho window's
+    // rows
+    constexpr int kJLanes = 8;
+    int *flist = reinterpret_cast<int *>(v);
+    int *fcount = flist + A.tile * A.tile;
+    if (tid == 0) *fcount = 0;
+    __syncthreads();
+    const int slot = wave_append(front, fcount);
+    if (front) flist[slot] = (py - y0) * A.tile + (px - x0);
+    __syncthreads();
+    const int nf = *fcount;
+    const int gj = tid / kJLanes, lj = tid % kJLanes;
+    for (int b0 = 0; b0 < nf; b0 += kBlock / kJLanes) {  // uniform trip count
+        const int item = b0 + gj;
         double den = 0.0, a = 0.0, b = 0.0, c = 0.0;
-        for (int dy = -rr; dy <= rr; ++dy)
-            for (int dx = -rr; dx <= rr; ++dx) {
-                const int ti = (ly + rr + dy) * RT + lx + rr + dx;
-                const int ui = (ly + rr + dy + 1 + rs) * RU + lx + rr + dx + 1 + rs;
-                if (!kn[ui]) continue;
-                const double w = wr[(dy + rr) * WR + dx + rr];
-                den += w;
-                a += w * T[3 * ti];
-                b += w * T[3 * ti + 1];
-                c += w * T[3 * ti + 2];
-            }
-        float2 g = make_float2(0.0f, 0.0f);
-        if (den > 0.0) g = coherence_direction(a / den, b / den, c / den, A.lambda);
-        reinterpret_cast<float2 *>(A.guide)[(long long)f * A.HW + (long long)py * W + px] = g;
+        int lx = 0, ly = 0;
+        if (item < nf) {
+            lx = flist[item] % A.tile;
+            ly = flist[item] / A.tile;
+            for (int dy = -rr + lj; dy <= rr; dy += kJLanes)
+                for (int dx = -rr; dx <= rr; ++dx) {
+                    const int ti = (ly + rr + dy) * RT + lx + rr + dx;
+                    const int ui = (ly + rr + dy + 1 + rs) * RU + lx + rr + dx + 1 + rs;
+                    if (!kn[ui]) continue;
+                    const double w = wr[(dy + rr) * WR + dx + rr];
+                    den += w;
+                    a += w * T[3 * ti];
+                    b += w * T[3 * ti + 1];
+                    c += w * T[3 * ti + 2];
+                }
+        }
+        den = gsum<kJLanes>(den);  // every lane of the block takes part
+        a = gsum<kJLanes>(a);
+        b = gsum<kJLanes>(b);
+        c = gsum<kJLanes>(c);
+        if (item < nf && lj == 0) {
+            float2 g = make_float2(0.0f, 0.0f);
+            if (den > 0.0) g = coherence_direction(a / den, b / den, c / den, A.lambda);
+            reinterpret_cast<float2 *>(A.guide)[(long long)f * A.HW + (long long)(y0 + ly) * W + x0 + lx] = g;
+        }
     }
 }
 
